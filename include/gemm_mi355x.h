@@ -1,0 +1,170 @@
+/*
+ * gemm_mi355x.h -- C ABI of the MI355X (gfx950) dense GEMM library.
+ *
+ * Operation (Ben-Nun et al., "Stateful Dataflow Multigraphs", SC'19):
+ * matrix multiplication is the map A[i,k]*B[k,j] followed by a reduction over
+ * k (Sec. 3.3, matrix-multiplication panel of Fig. "Write-Conflicts and
+ * Reductions"); the library computes it with the BLAS scalars of the external
+ * code call in Sec. 2.1:
+ *
+ *        C <- alpha * A*B + beta * C
+ *
+ * Conventions shared by every entry point
+ *   - Layout: row-major.  A is MxK with row stride lda >= max(1,K); B is KxN
+ *     with row stride ldb >= max(1,N); C is MxN with row stride ldc >= max(1,N).
+ *     Strides are in elements.  No transposes.
+ *   - Pointers named A, B, C, workspace, arena are DEVICE pointers owned by
+ *     the caller; the library never frees caller memory.  Pointers prefixed
+ *     h (hA, hC_out, ...) are host pointers.
+ *   - Every GPU entry point is asynchronous on the given stream.  Arguments
+ *     are checked before anything is enqueued; a rejected call enqueues
+ *     nothing.  The caller synchronises (stream or event) before reading C.
+ *   - beta == 0: C is write-only (NaN/Inf already in C never propagate).
+ *     alpha == 0 or K == 0: C <- beta*C and A, B are not read.
+ *     M == 0 or N == 0: no-op.  Quick returns take precedence over the
+ *     pointer checks (a pointer not needed may be NULL).
+ *   - Status: 0 = success; -i = argument i (1-based, in declaration order) is
+ *     invalid (BLAS xerbla convention); > 0 = runtime failure, see
+ *     GEMM_STATUS_*.  gemm_last_error() returns a thread-local message for the
+ *     most recent failure on the calling thread.
+ *   - Results are deterministic: the same call on the same inputs gives
+ *     bitwise-identical C (no atomics into C; the reduction order depends
+ *     only on M, N, K, the path and the tile configuration).
+ */
+#ifndef GEMM_MI355X_H
+#define GEMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int gemm_status;
+
+#define GEMM_STATUS_OK            0
+#define GEMM_STATUS_HIP_ERROR     1  /* a HIP runtime call or launch failed */
+#define GEMM_STATUS_NO_MEMORY     2  /* workspace/arena too small, allocation failed */
+#define GEMM_STATUS_NOT_READY     3  /* server_poll: request still in flight */
+#define GEMM_STATUS_UNSUPPORTED   4  /* e.g. device is not gfx950 */
+#define GEMM_STATUS_REJECTED      5  /* server: request can never fit the budget */
+#define GEMM_STATUS_UNKNOWN       6  /* server: unknown ticket */
+
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *gemm_last_error(void);
+
+/* Library version string. */
+const char *gemm_version(void);
+
+/* ------------------------------------------------------------------------
+ * Plain FP32 path (vector ALU).
+ * C <- alpha*A*B + beta*C with binary32 fused multiply-add accumulation in
+ * registers.  Tiling of the (i,j) map, LDS staging of A/B tiles with double
+ * buffering and per-lane register micro-tiles realise the MapTiling,
+ * LocalStorage, DoubleBuffering and Vectorization steps of the paper's
+ * transformation chain (Sec. 6.2, App. B table of transformations); alpha and
+ * beta are applied once in a peeled epilogue (ReducePeeling, Sec. 6.2).
+ * Arguments: 1 M, 2 N, 3 K, 4 alpha, 5 A, 6 lda, 7 B, 8 ldb, 9 beta, 10 C,
+ * 11 ldc, 12 stream.
+ * ---------------------------------------------------------------------- */
+gemm_status gemm_f32(int64_t M, int64_t N, int64_t K, float alpha,
+                     const float *A, int64_t lda, const float *B, int64_t ldb,
+                     float beta, float *C, int64_t ldc, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * FP32-accurate split-precision path on bf16 MFMA (not in the paper).
+ * Each binary32 operand element is split on the fly into bfloat16 planes
+ * a = a0 + a1 + a2 (round-to-nearest-even at every level, exact sum) while the
+ * tile is staged into LDS, and
+ *   n_products == 3 : acc += a0*b0 + a0*b1 + a1*b0
+ *   n_products == 6 : acc += the above + a0*b2 + a1*b1 + a2*b0
+ * with binary32 MFMA accumulation.  Arguments as gemm_f32, then
+ * 12 n_products (3 or 6), 13 stream.
+ * ---------------------------------------------------------------------- */
+gemm_status gemm_f32_3xbf16(int64_t M, int64_t N, int64_t K, float alpha,
+                            const float *A, int64_t lda, const float *B, int64_t ldb,
+                            float beta, float *C, int64_t ldc, int n_products,
+                            hipStream_t stream);
+
+/* The staging split alone, for verification: x (n floats, device) ->
+ * planes p0, p1, p2 (n bfloat16 bit patterns each, device; p2 may be NULL).
+ * Arguments: 1 n, 2 x, 3 p0, 4 p1, 5 p2, 6 stream. */
+gemm_status split_bf16x3(int64_t n, const float *x, uint16_t *p0, uint16_t *p1,
+                         uint16_t *p2, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Scaled FP8 path (not in the paper).  OCP E4M3 (max 448) operands with
+ * binary32 per-row scales of A and per-column scales of B:
+ *   sa[i] = max_k |A[i,k]| / 448,  sb[j] = max_k |B[k,j]| / 448 (0 -> 1),
+ *   qa = e4m3_rne_sat(A / sa),     qb = e4m3_rne_sat(B / sb),
+ *   C <- alpha * sa[i]*sb[j] * sum_k qa*qb + beta*C   (binary32 accumulation).
+ * The quantised operands and scales live in a caller-provided device
+ * workspace of at least gemm_fp8_workspace_bytes(M,N,K) bytes, laid out as
+ * [qa: M x Kp bytes][qb^T: N x Kp bytes][sa: M floats][sb: N floats], each
+ * region 256-byte aligned, Kp = K rounded up to a multiple of 64 (the padding
+ * holds zero codes).  qb is stored transposed (column j of B contiguous).
+ * Arguments: 1..11 as gemm_f32, 12 workspace, 13 ws_bytes, 14 stream.
+ * ---------------------------------------------------------------------- */
+size_t gemm_fp8_workspace_bytes(int64_t M, int64_t N, int64_t K);
+gemm_status gemm_fp8_scaled(int64_t M, int64_t N, int64_t K, float alpha,
+                            const float *A, int64_t lda, const float *B, int64_t ldb,
+                            float beta, float *C, int64_t ldc, void *workspace,
+                            size_t ws_bytes, hipStream_t stream);
+/* The two halves of gemm_fp8_scaled: quantise A and B into the workspace,
+ * then multiply the quantised operands already in the workspace.
+ * fp8_quantize arguments: 1 M, 2 N, 3 K, 4 A, 5 lda, 6 B, 7 ldb, 8 workspace,
+ * 9 ws_bytes, 10 stream.  gemm_fp8_prequantized arguments: 1 M, 2 N, 3 K,
+ * 4 alpha, 5 workspace, 6 ws_bytes, 7 beta, 8 C, 9 ldc, 10 stream. */
+gemm_status fp8_quantize(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                         const float *B, int64_t ldb, void *workspace, size_t ws_bytes,
+                         hipStream_t stream);
+gemm_status gemm_fp8_prequantized(int64_t M, int64_t N, int64_t K, float alpha,
+                                  const void *workspace, size_t ws_bytes, float beta,
+                                  float *C, int64_t ldc, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Tile configurations (for the autotuner and for per-configuration tests).
+ * Every configuration of a path computes the same operation; results may
+ * differ between configurations only by binary32 summation order.
+ * path: GEMM_PATH_F32, GEMM_PATH_3XBF16 or GEMM_PATH_FP8.
+ * gemm_run_config: arguments 1 path, 2 cfg (0 <= cfg < gemm_num_configs, or
+ * -1 for the library's default choice), then 3..13 as gemm_f32's 1..11,
+ * 14 n_products (3XBF16 only; ignored otherwise), 15 workspace, 16 ws_bytes
+ * (FP8 only; ignored otherwise), 17 stream.
+ * ---------------------------------------------------------------------- */
+#define GEMM_PATH_F32     0
+#define GEMM_PATH_3XBF16  1
+#define GEMM_PATH_FP8     2
+int gemm_num_configs(int path);
+const char *gemm_config_name(int path, int cfg);
+/* Default configuration the library picks for this shape on the current device. */
+int gemm_default_config(int path, int64_t M, int64_t N, int64_t K);
+gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, float alpha,
+                            const float *A, int64_t lda, const float *B, int64_t ldb,
+                            float beta, float *C, int64_t ldc, int n_products,
+                            void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * FP64 on-device error norm (verification only).
+ * C (binary32, MxN, row stride ldc) against Cref (binary64, MxN dense); den
+ * (binary64, MxN dense) may be NULL.  Writes four doubles to out (device):
+ *   out[0] = ||C - Cref||_F / ||Cref||_F  (||C - Cref||_F if Cref == 0)
+ *   out[1] = sum (C - Cref)^2,  out[2] = sum Cref^2,
+ *   out[3] = max |C - Cref| / den  (0/0 -> 0, x/0 -> inf), or max |C - Cref|
+ *            when den is NULL.
+ * The reduction order is fixed (deterministic).  workspace must hold
+ * err_norm_workspace_bytes() bytes of device memory.
+ * Arguments: 1 M, 2 N, 3 C, 4 ldc, 5 Cref, 6 den, 7 out, 8 workspace,
+ * 9 ws_bytes, 10 stream.
+ * ---------------------------------------------------------------------- */
+size_t err_norm_workspace_bytes(void);
+gemm_status err_norm_f64(int64_t M, int64_t N, const float *C, int64_t ldc,
+                         const double *Cref, const double *den, double *out,
+                         void *workspace, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEMM_MI355X_H */

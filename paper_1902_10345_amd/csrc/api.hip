@@ -1,0 +1,164 @@
+// api.hip -- the C-ABI boundary: argument validation, quick returns, dispatch.
+//
+// The validation pass mirrors the role of the SDFG validation step of the
+// compilation pipeline (Sec. 4.3): nothing is enqueued until every argument
+// has been checked.  Argument rules follow the BLAS-style call of the paper's
+// external-code example (Sec. 2.1), read as row-major with no transposes.
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+
+static thread_local std::string t_err;
+
+void set_error(const std::string &msg) { t_err = msg; }
+void clear_error() { t_err.clear(); }
+
+gemm_status hip_fail(const char *what, hipError_t e) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return GEMM_STATUS_HIP_ERROR;
+}
+
+gemm_status check_launch(const char *kernel) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(kernel, e);
+  return GEMM_STATUS_OK;
+}
+
+gemm_status bad_arg(int index, const char *fn, const char *why) {
+  set_error(std::string(fn) + ": argument " + std::to_string(index) + " " + why);
+  return -index;
+}
+
+int num_cus() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// Shared checks of the (M,N,K,alpha,A,lda,B,ldb,beta,C,ldc) prefix.
+// Returns 0 and sets `quick` when the call is fully handled by a quick path
+// decision (no-op or C <- beta*C); returns -index on a bad argument.
+struct Checked {
+  bool noop = false;      // M == 0 or N == 0
+  bool scale_only = false;  // alpha == 0 or K == 0
+};
+
+static gemm_status check_gemm_args(const char *fn, int64_t M, int64_t N, int64_t K, float alpha,
+                                   const float *A, int64_t lda, const float *B, int64_t ldb,
+                                   const float *C, int64_t ldc, Checked &ck) {
+  if (M < 0) return bad_arg(1, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(2, fn, "(N) must be >= 0");
+  if (K < 0) return bad_arg(3, fn, "(K) must be >= 0");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL)
+    return bad_arg(M > 0x7fffffffLL ? 1 : N > 0x7fffffffLL ? 2 : 3, fn, "exceeds 2^31-1");
+  if (lda < (K > 1 ? K : 1)) return bad_arg(6, fn, "(lda) must be >= max(1,K)");
+  if (ldb < (N > 1 ? N : 1)) return bad_arg(8, fn, "(ldb) must be >= max(1,N)");
+  if (ldc < (N > 1 ? N : 1)) return bad_arg(11, fn, "(ldc) must be >= max(1,N)");
+  if (M == 0 || N == 0) { ck.noop = true; return GEMM_STATUS_OK; }
+  if (!C) return bad_arg(10, fn, "(C) is NULL");
+  if (alpha == 0.0f || K == 0) { ck.scale_only = true; return GEMM_STATUS_OK; }
+  if (!A) return bad_arg(5, fn, "(A) is NULL");
+  if (!B) return bad_arg(7, fn, "(B) is NULL");
+  return GEMM_STATUS_OK;
+}
+
+}  // namespace mm
+
+using namespace mm;
+
+extern "C" {
+
+const char *gemm_last_error(void) { return t_err.c_str(); }
+
+const char *gemm_version(void) { return "gemm_mi355x 0.1 (gfx950)"; }
+
+gemm_status gemm_f32(int64_t M, int64_t N, int64_t K, float alpha, const float *A, int64_t lda,
+                     const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
+                     hipStream_t stream) {
+  clear_error();
+  Checked ck;
+  gemm_status st = check_gemm_args("gemm_f32", M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st || ck.noop) return st;
+  if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
+  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
+  return f32_run(g, f32_default_config(M, N, K), stream);
+}
+
+int gemm_num_configs(int path) {
+  switch (path) {
+    case GEMM_PATH_F32: return f32_num_configs();
+    default: return 0;
+  }
+}
+
+const char *gemm_config_name(int path, int cfg) {
+  if (cfg < 0 || cfg >= gemm_num_configs(path)) return "";
+  switch (path) {
+    case GEMM_PATH_F32: return f32_config(cfg).name;
+    default: return "";
+  }
+}
+
+int gemm_default_config(int path, int64_t M, int64_t N, int64_t K) {
+  switch (path) {
+    case GEMM_PATH_F32: return f32_default_config(M, N, K);
+    default: return -1;
+  }
+}
+
+gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, float alpha,
+                            const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+                            float *C, int64_t ldc, int n_products, void *workspace,
+                            size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_run_config";
+  if (gemm_num_configs(path) == 0) return bad_arg(1, fn, "(path) unknown or not built");
+  if (cfg < -1 || cfg >= gemm_num_configs(path)) return bad_arg(2, fn, "(cfg) out of range");
+  (void)n_products; (void)workspace; (void)ws_bytes;
+  Checked ck;
+  gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st < 0) st -= 2;  // argument index shifted by (path, cfg)
+  if (st || ck.noop) return st;
+  if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
+  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
+  if (cfg < 0) cfg = gemm_default_config(path, M, N, K);
+  switch (path) {
+    case GEMM_PATH_F32: return f32_run(g, cfg, stream);
+    default: return GEMM_STATUS_UNSUPPORTED;
+  }
+}
+
+size_t err_norm_workspace_bytes(void) { return errnorm_ws_bytes(); }
+
+gemm_status err_norm_f64(int64_t M, int64_t N, const float *C, int64_t ldc, const double *Cref,
+                         const double *den, double *out, void *workspace, size_t ws_bytes,
+                         hipStream_t stream) {
+  clear_error();
+  const char *fn = "err_norm_f64";
+  if (M < 0) return bad_arg(1, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(2, fn, "(N) must be >= 0");
+  if (M * N > 0 && !C) return bad_arg(3, fn, "(C) is NULL");
+  if (ldc < (N > 1 ? N : 1)) return bad_arg(4, fn, "(ldc) must be >= max(1,N)");
+  if (M * N > 0 && !Cref) return bad_arg(5, fn, "(Cref) is NULL");
+  if (!out) return bad_arg(7, fn, "(out) is NULL");
+  if (!workspace) return bad_arg(8, fn, "(workspace) is NULL");
+  if (ws_bytes < errnorm_ws_bytes()) return bad_arg(9, fn, "(ws_bytes) too small");
+  return errnorm_run(M, N, C, ldc, Cref, den, out, workspace, stream);
+}
+
+}  // extern "C"

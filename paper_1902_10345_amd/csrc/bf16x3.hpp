@@ -1,0 +1,253 @@
+// bf16x3.hpp -- tile body of the split-precision bf16 MFMA GEMM (gfx950).
+//
+// FP32-accurate C <- alpha*A*B + beta*C from bfloat16 matrix-core products.
+// Every binary32 element is split while its slab is staged into LDS,
+//   x = x0 + x1 (+ x2),  x0 = rne(x), x1 = rne(x - x0), x2 = rne(x - x0 - x1),
+// and the kernel accumulates, in binary32 on v_mfma_f32_32x32x16_bf16,
+//   NP == 2 (3 products): a0*b0 + a0*b1 + a1*b0
+//   NP == 3 (6 products): the above + a0*b2 + a1*b1 + a2*b0.
+//
+// Structure (the paper's MM transformation chain, Sec. 6.2, on CDNA4):
+//   MapTiling       BM x BN workgroup tile over (i, j); 2 x 2 waves, each a
+//                   WM x WN wave tile of 32 x 32 MFMA blocks; K in BK slabs.
+//   LocalStorage    A slab as [plane][BM][BK] and B slab transposed as
+//   DoubleBuffering [plane][BN][BK] bf16 in LDS, two stages; the slab t+1
+//                   global loads are issued before slab t is multiplied and
+//                   its split/stores are interleaved with slab t's MFMAs.
+//   Vectorization   128-bit global loads of A rows, 128-bit LDS writes and
+//                   ds_read_b128 fragment reads.
+//   ReducePeeling   alpha/beta applied once in the epilogue.
+// LDS rows are BK bf16 (BK*2 bytes) with an XOR swizzle of the 16-byte chunk
+// index, so that 16 consecutive rows read or written at one logical chunk
+// fall in distinct banks (for both 32- and 64-bank LDS organisations).
+#pragma once
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace bx3 {
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// Round-to-nearest-even split of a binary32 value into bfloat16 planes.
+__device__ __forceinline__ void split2(float x, __bf16 &h, __bf16 &l) {
+  h = (__bf16)x;
+  l = (__bf16)(x - (float)h);
+}
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = (__bf16)x;
+  const float r = x - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+// XOR swizzle of the 16-byte chunk index of an LDS row holding BK bf16.
+template <int BK>
+__device__ __forceinline__ int swz(int r) {
+  if constexpr (BK == 32) return ((r >> 1) ^ (r >> 3)) & 3;
+  else if constexpr (BK == 16) return ((r >> 2) ^ (r >> 3)) & 1;
+  else return 0;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int NP>
+struct Cfg {
+  static constexpr int NT = 256;            // 4 waves
+  static constexpr int WAVES_M = BM / WM;
+  static constexpr int WAVES_N = BN / WN;
+  static_assert(WAVES_M * WAVES_N == 4, "4 waves per workgroup");
+  static constexpr int FM = WM / 32;         // 32x32 blocks per wave along M
+  static constexpr int FN = WN / 32;
+  static constexpr int CH = BK / 8;          // 16-byte chunks per LDS row
+  static constexpr int KS = BK / 16;         // MFMA k-steps per slab
+  static constexpr int A_ITEMS = BM * CH / NT;   // (row, chunk) items per lane
+  static constexpr int B_ITEMS = BN * CH / NT;   // (col, chunk) items per lane
+  static_assert(A_ITEMS * NT == BM * CH && B_ITEMS * NT == BN * CH, "even split");
+  static constexpr int PLANE_A = BM * BK;    // bf16 elements per A plane
+  static constexpr int PLANE_B = BN * BK;
+  static constexpr int STAGE = NP * (PLANE_A + PLANE_B);  // bf16 per stage
+  static constexpr int LDS_BYTES = 2 * STAGE * 2;
+};
+
+// One output tile.  lds must hold Cfg::LDS_BYTES bytes (16-byte aligned).
+// VEC: lda % 4 == 0 and A 16-byte aligned (128-bit loads of A rows).
+template <int BM, int BN, int BK, int WM, int WN, int NP, bool VEC, bool BETA>
+__device__ __forceinline__ void tile(int M, int N, int K, float alpha,
+                                     const float *__restrict__ A, int64_t lda,
+                                     const float *__restrict__ B, int64_t ldb, float beta,
+                                     float *__restrict__ C, int64_t ldc, int m0, int n0,
+                                     __bf16 *lds) {
+  using G = Cfg<BM, BN, BK, WM, WN, NP>;
+  constexpr int NT = G::NT, CH = G::CH;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int Mr = M - m0, Nr = N - n0;
+  const float *Ab = A + (int64_t)m0 * lda;
+  const float *Bb = B + n0;
+
+  // ---- global -> registers ------------------------------------------------
+  float ra[G::A_ITEMS][8];
+  float rb[G::B_ITEMS][8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < G::A_ITEMS; ++i) {
+      const int idx = tid + NT * i;
+      const int r = idx / CH, k = k0 + (idx % CH) * 8;
+      const float *p = Ab + (int64_t)r * lda + k;
+      if (VEC && r < Mr && k + 7 < K) {
+        const float4 v0 = *reinterpret_cast<const float4 *>(p);
+        const float4 v1 = *reinterpret_cast<const float4 *>(p + 4);
+        ra[i][0] = v0.x; ra[i][1] = v0.y; ra[i][2] = v0.z; ra[i][3] = v0.w;
+        ra[i][4] = v1.x; ra[i][5] = v1.y; ra[i][6] = v1.z; ra[i][7] = v1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ra[i][e] = (r < Mr && k + e < K) ? p[e] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < G::B_ITEMS; ++i) {
+      const int idx = tid + NT * i;
+      const int n = idx % BN, k = k0 + (idx / BN) * 8;
+      const float *p = Bb + (int64_t)k * ldb + n;
+      const bool nin = n < Nr;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[i][e] = (nin && k + e < K) ? p[(int64_t)e * ldb] : 0.0f;
+    }
+  };
+
+  // ---- split + registers -> LDS (items [lo, hi) of each operand) ---------
+  auto sstore = [&](int stage, int part, int nparts) {
+    __bf16 *sA = lds + stage * G::STAGE;
+    __bf16 *sB = sA + NP * G::PLANE_A;
+#pragma unroll
+    for (int i = 0; i < G::A_ITEMS; ++i) {
+      if (i * nparts / G::A_ITEMS != part) continue;
+      const int idx = tid + NT * i;
+      const int r = idx / CH, c = idx % CH;
+      bf16x8 h, m, l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (NP == 2) split2(ra[i][e], h[e], m[e]);
+        else split3(ra[i][e], h[e], m[e], l[e]);
+      }
+      const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
+      *reinterpret_cast<bf16x8 *>(sA + off) = h;
+      *reinterpret_cast<bf16x8 *>(sA + G::PLANE_A + off) = m;
+      if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sA + 2 * G::PLANE_A + off) = l;
+    }
+#pragma unroll
+    for (int i = 0; i < G::B_ITEMS; ++i) {
+      if (i * nparts / G::B_ITEMS != part) continue;
+      const int idx = tid + NT * i;
+      const int n = idx % BN, c = idx / BN;
+      bf16x8 h, m, l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (NP == 2) split2(rb[i][e], h[e], m[e]);
+        else split3(rb[i][e], h[e], m[e], l[e]);
+      }
+      const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
+      *reinterpret_cast<bf16x8 *>(sB + off) = h;
+      *reinterpret_cast<bf16x8 *>(sB + G::PLANE_B + off) = m;
+      if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sB + 2 * G::PLANE_B + off) = l;
+    }
+  };
+
+  // ---- MFMA over one slab ------------------------------------------------
+  const int wm0 = (wave / G::WAVES_N) * WM;
+  const int wn0 = (wave % G::WAVES_N) * WN;
+  const int lrow = lane & 31, lgrp = lane >> 5;
+  f32x16 acc[G::FM][G::FN];
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+  auto mfma_step = [&](int stage, int ks) {
+    const __bf16 *sA = lds + stage * G::STAGE;
+    const __bf16 *sB = sA + NP * G::PLANE_A;
+    const int c = ks * 2 + lgrp;  // logical 16-byte chunk of this lane
+    bf16x8 a[NP][G::FM], b[NP][G::FN];
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i) {
+      const int r = wm0 + i * 32 + lrow;
+      const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) a[p][i] = *reinterpret_cast<const bf16x8 *>(sA + p * G::PLANE_A + off);
+    }
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int n = wn0 + j * 32 + lrow;
+      const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + off);
+    }
+    // Small products first, the leading product last.
+    if constexpr (NP == 3) {
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+  };
+
+  // ---- K loop -------------------------------------------------------------
+  const int KT = (K + BK - 1) / BK;
+  gload(0);
+  sstore(0, 0, 1);
+  __syncthreads();
+  for (int t = 0; t < KT; ++t) {
+    const bool more = t + 1 < KT;
+    if (more) gload((t + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < G::KS; ++ks) {
+      mfma_step(t & 1, ks);
+      if (more) sstore((t + 1) & 1, ks, G::KS);
+    }
+    __syncthreads();
+  }
+
+  // ---- peeled epilogue ----------------------------------------------------
+  // 32x32 block layout: lane l, element e -> row 8*(e/4) + 4*(l/32) + e%4,
+  // column l%32.
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int col = wn0 + j * 32 + lrow;
+      if (col >= Nr) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
+        if (row < Mr) {
+          float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
+          const float v = alpha * acc[i][j][e];
+          *p = BETA ? fmaf(beta, *p, v) : v;
+        }
+      }
+    }
+}
+
+}  // namespace bx3
+}  // namespace mm

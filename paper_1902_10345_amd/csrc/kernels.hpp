@@ -1,0 +1,39 @@
+// kernels.hpp -- internal interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace mm {
+
+// One GEMM problem after argument checking: C <- alpha*A*B + beta*C.
+struct GemmArgs {
+  int64_t M, N, K;
+  float alpha, beta;
+  const float *A;
+  int64_t lda;
+  const float *B;
+  int64_t ldb;
+  float *C;
+  int64_t ldc;
+};
+
+struct TileConfig {
+  int bm, bn, bk;
+  const char *name;
+};
+
+// Plain FP32 vector-ALU path.
+int f32_num_configs();
+const TileConfig &f32_config(int i);
+int f32_default_config(int64_t M, int64_t N, int64_t K);
+gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s);
+
+// C <- beta*C over an MxN block (alpha == 0 or K == 0 quick path).
+gemm_status scale_c(int64_t M, int64_t N, float beta, float *C, int64_t ldc, hipStream_t s);
+
+// FP64 error norm.
+size_t errnorm_ws_bytes();
+gemm_status errnorm_run(int64_t M, int64_t N, const float *C, int64_t ldc, const double *Cref,
+                        const double *den, double *out, void *ws, hipStream_t s);
+
+}  // namespace mm
