@@ -102,9 +102,11 @@ gemm_status split_bf16x3(int64_t n, const float *x, uint16_t *p0, uint16_t *p1,
  *   C <- alpha * sa[i]*sb[j] * sum_k qa*qb + beta*C   (binary32 accumulation).
  * The quantised operands and scales live in a caller-provided device
  * workspace of at least gemm_fp8_workspace_bytes(M,N,K) bytes, laid out as
- * [qa: M x Kp bytes][qb^T: N x Kp bytes][sa: M floats][sb: N floats], each
- * region 256-byte aligned, Kp = K rounded up to a multiple of 64 (the padding
- * holds zero codes).  qb is stored transposed (column j of B contiguous).
+ * [qa: M x Kp bytes][qb^T: N x Kp bytes][sa: M floats][sb: N floats]
+ * [N uint32 of scratch], each region 256-byte aligned, Kp = K rounded up to a
+ * multiple of 128 (the padding holds zero codes).  qb is stored transposed
+ * (column j of B contiguous).  Codes are E4M3 bit patterns (sign, 4 exponent
+ * bits with bias 7, 3 mantissa bits; 0x7E = 448, no infinities).
  * Arguments: 1..11 as gemm_f32, 12 workspace, 13 ws_bytes, 14 stream.
  * ---------------------------------------------------------------------- */
 size_t gemm_fp8_workspace_bytes(int64_t M, int64_t N, int64_t K);
@@ -123,6 +125,10 @@ gemm_status fp8_quantize(int64_t M, int64_t N, int64_t K, const float *A, int64_
 gemm_status gemm_fp8_prequantized(int64_t M, int64_t N, int64_t K, float alpha,
                                   const void *workspace, size_t ws_bytes, float beta,
                                   float *C, int64_t ldc, hipStream_t stream);
+/* The E4M3 encoder alone, for verification: codes[i] = e4m3_rne_sat(x[i])
+ * (NaN -> 0x7F; the sign of a value that rounds to zero is kept).
+ * Arguments: 1 n, 2 x (device floats), 3 codes (device bytes), 4 stream. */
+gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Tile configurations (for the autotuner and for per-configuration tests).

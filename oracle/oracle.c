@@ -98,9 +98,13 @@ static double bf16_rne(double x)
 
 float orc_bf16_rne(float x) { return (float)bf16_rne((double)x); }
 
-/* Three-way split a = a0 + a1 + a2 with a0 = rne(a), a1 = rne(a - a0),
- * a2 = a - a0 - a1.  For a finite binary32 a, a2 is itself a bfloat16 value
- * and the sum is exact.  Output planes hold the bfloat16 values as floats. */
+/* Three-way split with round-to-nearest-even at every level:
+ *   a0 = rne(a), r1 = a - a0 (exact), a1 = rne(r1), a2 = rne(r1 - a1).
+ * For |a| >= 2^-100 the last rounding is exact (r1 - a1 needs at most 8
+ * significant bits and lies in bfloat16's normal range), so a0 + a1 + a2 == a;
+ * below that the last plane may fall on bfloat16's subnormal grid (spacing
+ * 2^-133) and is rounded there.  Output planes hold the bfloat16 values as
+ * floats. */
 void orc_split_bf16x3(int64_t n, const float *x, float *p0, float *p1, float *p2)
 {
     for (int64_t t = 0; t < n; ++t) {
@@ -108,7 +112,7 @@ void orc_split_bf16x3(int64_t n, const float *x, float *p0, float *p1, float *p2
         double a0 = bf16_rne(a);
         double r1 = a - a0;
         double a1 = bf16_rne(r1);
-        double a2 = r1 - a1;
+        double a2 = bf16_rne(r1 - a1);
         p0[t] = (float)a0;
         p1[t] = (float)a1;
         p2[t] = (float)a2;

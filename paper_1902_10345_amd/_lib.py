@@ -59,6 +59,15 @@ def _sig(name, restype, *args):
 _sig("gemm_last_error", ctypes.c_char_p)
 _sig("gemm_version", ctypes.c_char_p)
 _sig("gemm_f32", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _vp)
+_sig("gemm_f32_3xbf16", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _int,
+     _vp)
+_sig("split_bf16x3", _int, _i64, _vp, _vp, _vp, _vp, _vp)
+_sig("gemm_fp8_workspace_bytes", _sz, _i64, _i64, _i64)
+_sig("gemm_fp8_scaled", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _vp,
+     _sz, _vp)
+_sig("fp8_quantize", _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
+_sig("gemm_fp8_prequantized", _int, _i64, _i64, _i64, _f32, _vp, _sz, _f32, _vp, _i64, _vp)
+_sig("fp8_e4m3_encode", _int, _i64, _vp, _vp, _vp)
 _sig("gemm_num_configs", _int, _int)
 _sig("gemm_config_name", ctypes.c_char_p, _int, _int)
 _sig("gemm_default_config", _int, _int, _i64, _i64, _i64)
@@ -90,12 +99,16 @@ def stream_handle(stream=None) -> int:
     return stream.cuda_stream
 
 
-def last_error() -> str:
+def gemm_last_error() -> str:
     return lib.gemm_last_error().decode()
 
 
-def version() -> str:
+def gemm_version() -> str:
     return lib.gemm_version().decode()
+
+
+last_error = gemm_last_error
+version = gemm_version
 
 
 def check(status: int) -> int:
@@ -107,6 +120,52 @@ def check(status: int) -> int:
 def gemm_f32(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     return check(lib.gemm_f32(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
                               stream_handle(stream)))
+
+
+def gemm_f32_3xbf16(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products=3, stream=None):
+    return check(lib.gemm_f32_3xbf16(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
+                                     n_products, stream_handle(stream)))
+
+
+def split_bf16x3(n, x, p0, p1, p2=None, stream=None):
+    return check(lib.split_bf16x3(n, ptr(x), ptr(p0), ptr(p1), ptr(p2), stream_handle(stream)))
+
+
+def gemm_fp8_workspace_bytes(M, N, K) -> int:
+    return int(lib.gemm_fp8_workspace_bytes(M, N, K))
+
+
+def gemm_fp8_scaled(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, workspace, ws_bytes,
+                    stream=None):
+    return check(lib.gemm_fp8_scaled(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
+                                     ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def fp8_quantize(M, N, K, A, lda, B, ldb, workspace, ws_bytes, stream=None):
+    return check(lib.fp8_quantize(M, N, K, ptr(A), lda, ptr(B), ldb, ptr(workspace), ws_bytes,
+                                  stream_handle(stream)))
+
+
+def gemm_fp8_prequantized(M, N, K, alpha, workspace, ws_bytes, beta, C, ldc, stream=None):
+    return check(lib.gemm_fp8_prequantized(M, N, K, alpha, ptr(workspace), ws_bytes, beta, ptr(C),
+                                           ldc, stream_handle(stream)))
+
+
+def fp8_e4m3_encode(n, x, codes, stream=None):
+    return check(lib.fp8_e4m3_encode(n, ptr(x), ptr(codes), stream_handle(stream)))
+
+
+def fp8_workspace_layout(M, N, K):
+    """Byte offsets of the workspace regions (qa, qbT, sa, sb) and Kp, as
+    documented in the header."""
+    def a256(x):
+        return (x + 255) & ~255
+    Kp = ((K + 127) // 128) * 128
+    qa = 0
+    qb = a256(qa + M * Kp)
+    sa = a256(qb + N * Kp)
+    sb = a256(sa + 4 * M)
+    return {"Kp": Kp, "qa": qa, "qb": qb, "sa": sa, "sb": sb}
 
 
 PATH_F32, PATH_3XBF16, PATH_FP8 = 0, 1, 2

@@ -99,9 +99,111 @@ gemm_status gemm_f32(int64_t M, int64_t N, int64_t K, float alpha, const float *
   return f32_run(g, f32_default_config(M, N, K), stream);
 }
 
+gemm_status gemm_f32_3xbf16(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                            int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                            int64_t ldc, int n_products, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_f32_3xbf16";
+  Checked ck;
+  gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st) return st;
+  if (n_products != 3 && n_products != 6) return bad_arg(12, fn, "(n_products) must be 3 or 6");
+  if (ck.noop) return GEMM_STATUS_OK;
+  if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
+  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
+  return bx3_run(g, bx3_default_config(M, N, K, n_products), stream);
+}
+
+gemm_status split_bf16x3(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
+                         hipStream_t stream) {
+  clear_error();
+  const char *fn = "split_bf16x3";
+  if (n < 0) return bad_arg(1, fn, "(n) must be >= 0");
+  if (n == 0) return GEMM_STATUS_OK;
+  if (!x) return bad_arg(2, fn, "(x) is NULL");
+  if (!p0) return bad_arg(3, fn, "(p0) is NULL");
+  if (!p1) return bad_arg(4, fn, "(p1) is NULL");
+  return bx3_split(n, x, p0, p1, p2, stream);
+}
+
+size_t gemm_fp8_workspace_bytes(int64_t M, int64_t N, int64_t K) {
+  if (M < 0 || N < 0 || K < 0) return 0;
+  return fp8_ws_bytes(M, N, K);
+}
+
+static gemm_status fp8_check_ws(const char *fn, int idx, int64_t M, int64_t N, int64_t K,
+                                const void *ws, size_t ws_bytes) {
+  if (!ws) return bad_arg(idx, fn, "(workspace) is NULL");
+  if (((uintptr_t)ws & 255) != 0) return bad_arg(idx, fn, "(workspace) must be 256-byte aligned");
+  if (ws_bytes < fp8_ws_bytes(M, N, K)) return bad_arg(idx + 1, fn, "(ws_bytes) too small");
+  return GEMM_STATUS_OK;
+}
+
+gemm_status gemm_fp8_scaled(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                            int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                            int64_t ldc, void *workspace, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_fp8_scaled";
+  Checked ck;
+  gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st || ck.noop) return st;
+  if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
+  if ((st = fp8_check_ws(fn, 12, M, N, K, workspace, ws_bytes))) return st;
+  if ((st = fp8_quantize_run(M, N, K, A, lda, B, ldb, workspace, stream))) return st;
+  return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
+}
+
+gemm_status fp8_quantize(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                         const float *B, int64_t ldb, void *workspace, size_t ws_bytes,
+                         hipStream_t stream) {
+  clear_error();
+  const char *fn = "fp8_quantize";
+  if (M < 0) return bad_arg(1, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(2, fn, "(N) must be >= 0");
+  if (K < 0) return bad_arg(3, fn, "(K) must be >= 0");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL) return bad_arg(1, fn, "size exceeds 2^31-1");
+  if (M > 0 && K > 0 && !A) return bad_arg(4, fn, "(A) is NULL");
+  if (lda < (K > 1 ? K : 1)) return bad_arg(5, fn, "(lda) must be >= max(1,K)");
+  if (N > 0 && K > 0 && !B) return bad_arg(6, fn, "(B) is NULL");
+  if (ldb < (N > 1 ? N : 1)) return bad_arg(7, fn, "(ldb) must be >= max(1,N)");
+  gemm_status st = fp8_check_ws(fn, 8, M, N, K, workspace, ws_bytes);
+  if (st) return st;
+  return fp8_quantize_run(M, N, K, A, lda, B, ldb, workspace, stream);
+}
+
+gemm_status gemm_fp8_prequantized(int64_t M, int64_t N, int64_t K, float alpha,
+                                  const void *workspace, size_t ws_bytes, float beta, float *C,
+                                  int64_t ldc, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_fp8_prequantized";
+  if (M < 0) return bad_arg(1, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(2, fn, "(N) must be >= 0");
+  if (K < 0) return bad_arg(3, fn, "(K) must be >= 0");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL) return bad_arg(1, fn, "size exceeds 2^31-1");
+  gemm_status st = fp8_check_ws(fn, 5, M, N, K, workspace, ws_bytes);
+  if (st) return st;
+  if (ldc < (N > 1 ? N : 1)) return bad_arg(9, fn, "(ldc) must be >= max(1,N)");
+  if (M == 0 || N == 0) return GEMM_STATUS_OK;
+  if (!C) return bad_arg(8, fn, "(C) is NULL");
+  if (alpha == 0.0f || K == 0) return scale_c(M, N, beta, C, ldc, stream);
+  return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
+}
+
+gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream_t stream) {
+  clear_error();
+  const char *fn = "fp8_e4m3_encode";
+  if (n < 0) return bad_arg(1, fn, "(n) must be >= 0");
+  if (n == 0) return GEMM_STATUS_OK;
+  if (!x) return bad_arg(2, fn, "(x) is NULL");
+  if (!codes) return bad_arg(3, fn, "(codes) is NULL");
+  return fp8_encode_run(n, x, codes, stream);
+}
+
 int gemm_num_configs(int path) {
   switch (path) {
     case GEMM_PATH_F32: return f32_num_configs();
+    case GEMM_PATH_3XBF16: return bx3_num_configs();
+    case GEMM_PATH_FP8: return 1;
     default: return 0;
   }
 }
@@ -110,6 +212,8 @@ const char *gemm_config_name(int path, int cfg) {
   if (cfg < 0 || cfg >= gemm_num_configs(path)) return "";
   switch (path) {
     case GEMM_PATH_F32: return f32_config(cfg).name;
+    case GEMM_PATH_3XBF16: return bx3_config(cfg).name;
+    case GEMM_PATH_FP8: return "fp8_256x256x128_w128x128";
     default: return "";
   }
 }
@@ -117,6 +221,8 @@ const char *gemm_config_name(int path, int cfg) {
 int gemm_default_config(int path, int64_t M, int64_t N, int64_t K) {
   switch (path) {
     case GEMM_PATH_F32: return f32_default_config(M, N, K);
+    case GEMM_PATH_3XBF16: return bx3_default_config(M, N, K, 3);
+    case GEMM_PATH_FP8: return 0;
     default: return -1;
   }
 }
@@ -129,16 +235,31 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
   const char *fn = "gemm_run_config";
   if (gemm_num_configs(path) == 0) return bad_arg(1, fn, "(path) unknown or not built");
   if (cfg < -1 || cfg >= gemm_num_configs(path)) return bad_arg(2, fn, "(cfg) out of range");
-  (void)n_products; (void)workspace; (void)ws_bytes;
   Checked ck;
   gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
-  if (st < 0) st -= 2;  // argument index shifted by (path, cfg)
+  if (st < 0) {  // argument index shifted by (path, cfg)
+    set_error(std::string(fn) + ": argument " + std::to_string(2 - st) + " invalid");
+    return st - 2;
+  }
+  if (path == GEMM_PATH_3XBF16) {
+    if (n_products != 3 && n_products != 6) return bad_arg(14, fn, "(n_products) must be 3 or 6");
+    if (cfg >= 0 && bx3_config_products(cfg) != n_products)
+      return bad_arg(14, fn, "(n_products) does not match the configuration");
+  }
   if (st || ck.noop) return st;
   if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
+  if (path == GEMM_PATH_FP8) {
+    if ((st = fp8_check_ws(fn, 15, M, N, K, workspace, ws_bytes))) return st;
+    if ((st = fp8_quantize_run(M, N, K, A, lda, B, ldb, workspace, stream))) return st;
+    return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
+  }
   GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
-  if (cfg < 0) cfg = gemm_default_config(path, M, N, K);
+  if (cfg < 0)
+    cfg = path == GEMM_PATH_3XBF16 ? bx3_default_config(M, N, K, n_products)
+                                   : gemm_default_config(path, M, N, K);
   switch (path) {
     case GEMM_PATH_F32: return f32_run(g, cfg, stream);
+    case GEMM_PATH_3XBF16: return bx3_run(g, cfg, stream);
     default: return GEMM_STATUS_UNSUPPORTED;
   }
 }

@@ -50,20 +50,21 @@ __device__ __forceinline__ int swz(int r) {
   else return 0;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int NP>
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
 struct Cfg {
-  static constexpr int NT = 256;            // 4 waves
+  static constexpr int NT = 64 * NW;          // lanes per workgroup
   static constexpr int WAVES_M = BM / WM;
   static constexpr int WAVES_N = BN / WN;
-  static_assert(WAVES_M * WAVES_N == 4, "4 waves per workgroup");
-  static constexpr int FM = WM / 32;         // 32x32 blocks per wave along M
+  static_assert(WAVES_M * WAVES_N == NW, "wave grid must cover the tile");
+  static constexpr int FM = WM / 32;          // 32x32 blocks per wave along M
   static constexpr int FN = WN / 32;
-  static constexpr int CH = BK / 8;          // 16-byte chunks per LDS row
-  static constexpr int KS = BK / 16;         // MFMA k-steps per slab
-  static constexpr int A_ITEMS = BM * CH / NT;   // (row, chunk) items per lane
-  static constexpr int B_ITEMS = BN * CH / NT;   // (col, chunk) items per lane
+  static constexpr int CH = BK / 8;           // 16-byte chunks per LDS row
+  static constexpr int KS = BK / 16;          // MFMA k-steps per slab
+  static constexpr int A_ITEMS = BM * CH / NT;    // (row, chunk) items per lane
+  static constexpr int B_ITEMS = BN * CH / NT;    // (col, chunk) items per lane
   static_assert(A_ITEMS * NT == BM * CH && B_ITEMS * NT == BN * CH, "even split");
-  static constexpr int PLANE_A = BM * BK;    // bf16 elements per A plane
+  static_assert(BN % 64 == 0 || NT % BN == 0, "B chunk index must be wave-uniform");
+  static constexpr int PLANE_A = BM * BK;     // bf16 elements per A plane
   static constexpr int PLANE_B = BN * BK;
   static constexpr int STAGE = NP * (PLANE_A + PLANE_B);  // bf16 per stage
   static constexpr int LDS_BYTES = 2 * STAGE * 2;
@@ -71,65 +72,103 @@ struct Cfg {
 
 // One output tile.  lds must hold Cfg::LDS_BYTES bytes (16-byte aligned).
 // VEC: lda % 4 == 0 and A 16-byte aligned (128-bit loads of A rows).
-template <int BM, int BN, int BK, int WM, int WN, int NP, bool VEC, bool BETA>
+// Interior slabs (tile fully inside M x N and a whole BK slab of K) take an
+// unpredicated load path; edge slabs take a guarded path that reads zeros
+// outside the matrices.  The choice is uniform across the workgroup.
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA>
 __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
                                      const float *__restrict__ A, int64_t lda,
                                      const float *__restrict__ B, int64_t ldb, float beta,
                                      float *__restrict__ C, int64_t ldc, int m0, int n0,
                                      __bf16 *lds) {
-  using G = Cfg<BM, BN, BK, WM, WN, NP>;
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
   constexpr int NT = G::NT, CH = G::CH;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int Mr = M - m0, Nr = N - n0;
+  const bool interior = Mr >= BM && Nr >= BN;
   const float *Ab = A + (int64_t)m0 * lda;
   const float *Bb = B + n0;
+  // 32-bit element offsets of this lane's A items inside the tile's row panel
+  // (the launcher guarantees BM * lda + K < 2^31).
+  int a_off[G::A_ITEMS];
+#pragma unroll
+  for (int i = 0; i < G::A_ITEMS; ++i) {
+    const int idx = tid + NT * i;
+    a_off[i] = (idx / CH) * (int)lda + (idx % CH) * 8;
+  }
 
   // ---- global -> registers ------------------------------------------------
   float ra[G::A_ITEMS][8];
   float rb[G::B_ITEMS][8];
   auto gload = [&](int k0) {
+    const bool full = interior && k0 + BK <= K;
+    if (full) {
+      const float *Ak = Ab + k0;
 #pragma unroll
-    for (int i = 0; i < G::A_ITEMS; ++i) {
-      const int idx = tid + NT * i;
-      const int r = idx / CH, k = k0 + (idx % CH) * 8;
-      const float *p = Ab + (int64_t)r * lda + k;
-      if (VEC && r < Mr && k + 7 < K) {
-        const float4 v0 = *reinterpret_cast<const float4 *>(p);
-        const float4 v1 = *reinterpret_cast<const float4 *>(p + 4);
-        ra[i][0] = v0.x; ra[i][1] = v0.y; ra[i][2] = v0.z; ra[i][3] = v0.w;
-        ra[i][4] = v1.x; ra[i][5] = v1.y; ra[i][6] = v1.z; ra[i][7] = v1.w;
-      } else {
+      for (int i = 0; i < G::A_ITEMS; ++i) {
+        const float *p = Ak + a_off[i];
+        if (VEC) {
+          const float4 v0 = *reinterpret_cast<const float4 *>(p);
+          const float4 v1 = *reinterpret_cast<const float4 *>(p + 4);
+          ra[i][0] = v0.x; ra[i][1] = v0.y; ra[i][2] = v0.z; ra[i][3] = v0.w;
+          ra[i][4] = v1.x; ra[i][5] = v1.y; ra[i][6] = v1.z; ra[i][7] = v1.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) ra[i][e] = p[e];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G::B_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int n = idx % BN;
+        const int c = __builtin_amdgcn_readfirstlane(idx / BN);  // wave-uniform
+        const float *Bk = Bb + (int64_t)(k0 + 8 * c) * ldb;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rb[i][e] = Bk[(int64_t)e * ldb + n];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < G::A_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int r = idx / CH, k = k0 + (idx % CH) * 8;
+        const float *p = Ab + (int64_t)r * lda + k;
 #pragma unroll
         for (int e = 0; e < 8; ++e) ra[i][e] = (r < Mr && k + e < K) ? p[e] : 0.0f;
       }
-    }
 #pragma unroll
-    for (int i = 0; i < G::B_ITEMS; ++i) {
-      const int idx = tid + NT * i;
-      const int n = idx % BN, k = k0 + (idx / BN) * 8;
-      const float *p = Bb + (int64_t)k * ldb + n;
-      const bool nin = n < Nr;
+      for (int i = 0; i < G::B_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int n = idx % BN, k = k0 + (idx / BN) * 8;
+        const float *p = Bb + (int64_t)k * ldb + n;
+        const bool nin = n < Nr;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[i][e] = (nin && k + e < K) ? p[(int64_t)e * ldb] : 0.0f;
+        for (int e = 0; e < 8; ++e) rb[i][e] = (nin && k + e < K) ? p[(int64_t)e * ldb] : 0.0f;
+      }
     }
   };
 
-  // ---- split + registers -> LDS (items [lo, hi) of each operand) ---------
-  auto sstore = [&](int stage, int part, int nparts) {
+  // ---- split + registers -> LDS --------------------------------------------
+  auto split8 = [&](const float (&x)[8], bf16x8 &h, bf16x8 &m, bf16x8 &l) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 x0, x1, x2;
+      if constexpr (NP == 2) split2(x[e], x0, x1);
+      else split3(x[e], x0, x1, x2);
+      h[e] = x0;
+      m[e] = x1;
+      if constexpr (NP == 3) l[e] = x2;
+    }
+  };
+  auto sstore = [&](int stage) {
     __bf16 *sA = lds + stage * G::STAGE;
     __bf16 *sB = sA + NP * G::PLANE_A;
 #pragma unroll
     for (int i = 0; i < G::A_ITEMS; ++i) {
-      if (i * nparts / G::A_ITEMS != part) continue;
       const int idx = tid + NT * i;
       const int r = idx / CH, c = idx % CH;
       bf16x8 h, m, l;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if constexpr (NP == 2) split2(ra[i][e], h[e], m[e]);
-        else split3(ra[i][e], h[e], m[e], l[e]);
-      }
+      split8(ra[i], h, m, l);
       const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
       *reinterpret_cast<bf16x8 *>(sA + off) = h;
       *reinterpret_cast<bf16x8 *>(sA + G::PLANE_A + off) = m;
@@ -137,15 +176,10 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
     }
 #pragma unroll
     for (int i = 0; i < G::B_ITEMS; ++i) {
-      if (i * nparts / G::B_ITEMS != part) continue;
       const int idx = tid + NT * i;
       const int n = idx % BN, c = idx / BN;
       bf16x8 h, m, l;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if constexpr (NP == 2) split2(rb[i][e], h[e], m[e]);
-        else split3(rb[i][e], h[e], m[e], l[e]);
-      }
+      split8(rb[i], h, m, l);
       const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
       *reinterpret_cast<bf16x8 *>(sB + off) = h;
       *reinterpret_cast<bf16x8 *>(sB + G::PLANE_B + off) = m;
@@ -184,16 +218,24 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
 #pragma unroll
       for (int p = 0; p < NP; ++p) b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + off);
     }
-    // Small products first, the leading product last.
+    // Small products first, the leading product last; consecutive MFMAs go
+    // to different accumulator blocks.
     if constexpr (NP == 3) {
 #pragma unroll
       for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < G::FN; ++j) {
+        for (int j = 0; j < G::FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-        }
     }
 #pragma unroll
     for (int i = 0; i < G::FM; ++i)
@@ -212,19 +254,17 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
   };
 
-  // ---- K loop -------------------------------------------------------------
+  // ---- K loop: loads of slab t+1 in flight during slab t's MFMAs ---------
   const int KT = (K + BK - 1) / BK;
   gload(0);
-  sstore(0, 0, 1);
+  sstore(0);
   __syncthreads();
   for (int t = 0; t < KT; ++t) {
     const bool more = t + 1 < KT;
     if (more) gload((t + 1) * BK);
 #pragma unroll
-    for (int ks = 0; ks < G::KS; ++ks) {
-      mfma_step(t & 1, ks);
-      if (more) sstore((t + 1) & 1, ks, G::KS);
-    }
+    for (int ks = 0; ks < G::KS; ++ks) mfma_step(t & 1, ks);
+    if (more) sstore((t + 1) & 1);
     __syncthreads();
   }
 
@@ -236,11 +276,11 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
 #pragma unroll
     for (int j = 0; j < G::FN; ++j) {
       const int col = wn0 + j * 32 + lrow;
-      if (col >= Nr) continue;
+      if (!interior && col >= Nr) continue;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
-        if (row < Mr) {
+        if (interior || row < Mr) {
           float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
           const float v = alpha * acc[i][j][e];
           *p = BETA ? fmaf(beta, *p, v) : v;

@@ -1,0 +1,364 @@
+// k_fp8.hip -- scaled FP8 (OCP E4M3) GEMM on gfx950 matrix cores.
+//
+//   sa[i] = max_k |A[i,k]| / 448,  sb[j] = max_k |B[k,j]| / 448  (0 -> 1)
+//   qa = e4m3(A / sa),  qb = e4m3(B / sb)   (round to nearest even, saturating)
+//   C <- alpha * sa[i] * sb[j] * sum_k qa*qb + beta*C   (binary32 accumulation)
+//
+// Workspace layout (each region 256-byte aligned, Kp = K rounded up to 128):
+//   [qa: M x Kp bytes][qbT: N x Kp bytes][sa: M floats][sb: N floats]
+//   [amax bits of B's columns: N uint32]
+// qbT is B's code matrix transposed (column j contiguous), so both operands are
+// k-contiguous and stage into LDS without a transpose.  Codes in [K, Kp) are 0.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace fp8 {
+
+constexpr int KP_ALIGN = 128;
+
+struct Layout {
+  int64_t Kp;
+  size_t qa, qb, sa, sb, amax, total;
+};
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout(int64_t M, int64_t N, int64_t K) {
+  Layout L;
+  L.Kp = ((K + KP_ALIGN - 1) / KP_ALIGN) * KP_ALIGN;
+  size_t off = 0;
+  L.qa = off; off = align256(off + (size_t)(M * L.Kp));
+  L.qb = off; off = align256(off + (size_t)(N * L.Kp));
+  L.sa = off; off = align256(off + sizeof(float) * (size_t)M);
+  L.sb = off; off = align256(off + sizeof(float) * (size_t)N);
+  L.amax = off; off = align256(off + sizeof(uint32_t) * (size_t)N);
+  L.total = off;
+  return L;
+}
+
+// Binary32 -> E4M3 code, round to nearest even, saturating at +-448.  NaN ->
+// 0x7F.  The sign bit is kept, so negative values that round to zero give 0x80.
+__device__ __forceinline__ uint32_t e4m3_encode(float x) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, x);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t a = u & 0x7fffffffu;
+  if (a > 0x7f800000u) return 0x7fu;                 // NaN
+  if (a >= 0x43e00000u) return sign | 0x7eu;         // |x| >= 448: saturate
+  if (a < 0x3c800000u) {                             // |x| < 2^-6: subnormal grid 2^-9
+    const float q = __builtin_bit_cast(float, a) * 512.0f;   // exact power-of-two scale
+    const uint32_t m = (uint32_t)__builtin_rintf(q);         // ties to even; 0..8
+    return sign | m;                                  // m == 8 is the smallest normal
+  }
+  // Normal range: round the 23-bit mantissa to 3 bits, ties to even; a carry
+  // out of the mantissa moves to the next binade by itself.
+  const uint32_t bias = 0x7ffffu + ((a >> 20) & 1u);
+  const uint32_t r = (a + bias) >> 20;               // exponent(8) | mantissa(3)
+  const uint32_t code = r - ((127u - 7u) << 3);      // rebias the exponent
+  return sign | (code > 0x7eu ? 0x7eu : code);
+}
+
+__device__ __forceinline__ float warp_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One workgroup per row of A: amax over the row, scale, then codes of the row
+// (16 consecutive k per lane per step, one 16-byte store).
+__global__ __launch_bounds__(256) void quant_rows_kernel(int M, int K, int64_t Kp,
+                                                         const float *__restrict__ A, int64_t lda,
+                                                         uint8_t *__restrict__ qa,
+                                                         float *__restrict__ sa) {
+  __shared__ float red[4];
+  const int i = blockIdx.x;
+  const float *row = A + (int64_t)i * lda;
+  float m = 0.0f;
+  for (int k = threadIdx.x; k < K; k += 256) m = fmaxf(m, fabsf(row[k]));
+  m = warp_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float s = (m == 0.0f) ? 1.0f : m / 448.0f;
+  if (threadIdx.x == 0) sa[i] = s;
+  uint8_t *q = qa + (int64_t)i * Kp;
+  for (int64_t k0 = (int64_t)threadIdx.x * 16; k0 < Kp; k0 += 256 * 16) {
+    uint32_t w[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t k = k0 + g * 4 + e;
+        const uint32_t c = k < K ? e4m3_encode(row[k] / s) : 0u;
+        word |= c << (8 * e);
+      }
+      w[g] = word;
+    }
+    *reinterpret_cast<uint4 *>(q + k0) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0u;
+}
+
+// Column amax of B over a K range: grid (ceil(N/256), ksplit).  Non-negative
+// binary32 values order like their bit patterns, so atomicMax on the bits is
+// an exact, order-independent maximum.
+__global__ __launch_bounds__(256) void col_amax_kernel(int K, int N, const float *__restrict__ B,
+                                                       int64_t ldb, int krange,
+                                                       uint32_t *__restrict__ amax_bits) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int k0 = blockIdx.y * krange;
+  const int k1 = min(K, k0 + krange);
+  float m = 0.0f;
+  for (int k = k0; k < k1; ++k) m = fmaxf(m, fabsf(B[(int64_t)k * ldb + j]));
+  atomicMax(amax_bits + j, __builtin_bit_cast(uint32_t, m));
+}
+
+// Quantise a 64(k) x 64(n) block of B with the column scales and store it
+// transposed into qbT (row j holds column j of B, k contiguous).
+__global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t Kp,
+                                                           const float *__restrict__ B, int64_t ldb,
+                                                           const uint32_t *__restrict__ amax_bits,
+                                                           uint8_t *__restrict__ qbT,
+                                                           float *__restrict__ sb) {
+  __shared__ uint8_t tileT[64][64 + 16];
+  const int kb = blockIdx.x * 64, nb = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int j = nb + tx;
+  float s = 1.0f;
+  if (j < N) {
+    const float m = __builtin_bit_cast(float, amax_bits[j]);
+    s = (m == 0.0f) ? 1.0f : m / 448.0f;
+    if (blockIdx.x == 0 && ty == 0) sb[j] = s;
+  }
+#pragma unroll 4
+  for (int r = ty; r < 64; r += 4) {
+    const int k = kb + r;
+    const uint32_t c = (k < K && j < N) ? e4m3_encode(B[(int64_t)k * ldb + j] / s) : 0u;
+    tileT[tx][r] = (uint8_t)c;
+  }
+  __syncthreads();
+  // 64 rows (n) x 64 bytes (k): each lane stores 16 bytes.
+  const int row = threadIdx.x >> 2, seg = (threadIdx.x & 3) * 16;
+  const int jn = nb + row;
+  if (jn < N) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&tileT[row][seg]);
+    *reinterpret_cast<uint4 *>(qbT + (int64_t)jn * Kp + kb + seg) =
+        make_uint4(src[0], src[1], src[2], src[3]);
+  }
+}
+
+// ---------------------------------------------------------------- GEMM ----
+// 256 x 256 tile, 128-byte K slabs, 2 x 2 waves of 128 x 128, MFMA
+// v_mfma_f32_32x32x64_f8f6f4 with both operands E4M3.  LDS rows are 128
+// bytes with an XOR swizzle of the 16-byte chunk index.
+template <int BM, int BN, int WM, int WN>
+struct Fp8Cfg {
+  static constexpr int NT = 256;
+  static constexpr int BK = 128;
+  static constexpr int WAVES_N = BN / WN;
+  static_assert((BM / WM) * WAVES_N == 4, "4 waves");
+  static constexpr int FM = WM / 32, FN = WN / 32;
+  static constexpr int A_CH = BM * BK / 16 / NT;   // 16-byte chunks per lane per slab
+  static constexpr int B_CH = BN * BK / 16 / NT;
+  static constexpr int STAGE = (BM + BN) * BK;     // bytes
+  static constexpr int LDS_BYTES = 2 * STAGE;
+};
+
+__device__ __forceinline__ int swz8(int r) { return (r ^ (r >> 3)) & 7; }
+
+template <int BM, int BN, int WM, int WN, bool BETA>
+__global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(
+    int M, int N, int64_t Kp, float alpha, const uint8_t *__restrict__ qa,
+    const uint8_t *__restrict__ qbT, const float *__restrict__ sa, const float *__restrict__ sb,
+    float beta, float *__restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+  using G = Fp8Cfg<BM, BN, WM, WN>;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[G::LDS_BYTES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int Mr = M - m0, Nr = N - n0;
+
+  uint4 ra[G::A_CH], rb[G::B_CH];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < G::A_CH; ++i) {
+      const int idx = tid + G::NT * i;
+      const int r = idx >> 3, c = idx & 7;
+      ra[i] = r < Mr ? *reinterpret_cast<const uint4 *>(qa + (int64_t)(m0 + r) * Kp + k0 + c * 16)
+                     : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < G::B_CH; ++i) {
+      const int idx = tid + G::NT * i;
+      const int r = idx >> 3, c = idx & 7;
+      rb[i] = r < Nr ? *reinterpret_cast<const uint4 *>(qbT + (int64_t)(n0 + r) * Kp + k0 + c * 16)
+                     : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto sstore = [&](int stage) {
+    uint8_t *sA = lds + stage * G::STAGE;
+    uint8_t *sB = sA + BM * G::BK;
+#pragma unroll
+    for (int i = 0; i < G::A_CH; ++i) {
+      const int idx = tid + G::NT * i;
+      const int r = idx >> 3, c = idx & 7;
+      *reinterpret_cast<uint4 *>(sA + r * G::BK + ((c ^ swz8(r)) << 4)) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < G::B_CH; ++i) {
+      const int idx = tid + G::NT * i;
+      const int r = idx >> 3, c = idx & 7;
+      *reinterpret_cast<uint4 *>(sB + r * G::BK + ((c ^ swz8(r)) << 4)) = rb[i];
+    }
+  };
+
+  const int wm0 = (wave / G::WAVES_N) * WM, wn0 = (wave % G::WAVES_N) * WN;
+  const int lrow = lane & 31, lgrp = lane >> 5;
+  f32x16 acc[G::FM][G::FN];
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+  auto mfma_step = [&](int stage, int ks) {
+    const uint8_t *sA = lds + stage * G::STAGE;
+    const uint8_t *sB = sA + BM * G::BK;
+    // lane holds 32 consecutive k (two 16-byte chunks) of its row / column
+    const int c0 = ks * 4 + lgrp * 2;
+    i32x8 a[G::FM], b[G::FN];
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i) {
+      const int r = wm0 + i * 32 + lrow;
+      const uint4 lo = *reinterpret_cast<const uint4 *>(sA + r * G::BK + ((c0 ^ swz8(r)) << 4));
+      const uint4 hi = *reinterpret_cast<const uint4 *>(sA + r * G::BK + (((c0 + 1) ^ swz8(r)) << 4));
+      a[i] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int r = wn0 + j * 32 + lrow;
+      const uint4 lo = *reinterpret_cast<const uint4 *>(sB + r * G::BK + ((c0 ^ swz8(r)) << 4));
+      const uint4 hi = *reinterpret_cast<const uint4 *>(sB + r * G::BK + (((c0 + 1) ^ swz8(r)) << 4));
+      b[j] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+        // formats: 0 = E4M3 for both operands; no block scaling
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                     0, 0, 0, 0);
+  };
+
+  const int KT = (int)(Kp / G::BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < KT; ++t) {
+    const bool more = t + 1 < KT;
+    if (more) gload((int64_t)(t + 1) * G::BK);
+    mfma_step(t & 1, 0);
+    mfma_step(t & 1, 1);
+    if (more) sstore((t + 1) & 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int col = wn0 + j * 32 + lrow;
+      if (col >= Nr) continue;
+      const float sj = sb[n0 + col] * alpha;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
+        if (row < Mr) {
+          float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
+          const float v = (sa[m0 + row] * sj) * acc[i][j][e];
+          *p = BETA ? fmaf(beta, *p, v) : v;
+        }
+      }
+    }
+}
+
+// Raw conversion, for verification of the encoder.
+__global__ __launch_bounds__(256) void encode_kernel(int64_t n, const float *__restrict__ x,
+                                                     uint8_t *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = (uint8_t)e4m3_encode(x[i]);
+}
+
+}  // namespace fp8
+
+size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K) { return fp8::layout(M, N, K).total; }
+int64_t fp8_kp(int64_t K) { return fp8::layout(0, 0, K).Kp; }
+
+gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                             const float *B, int64_t ldb, void *ws, hipStream_t s) {
+  const fp8::Layout L = fp8::layout(M, N, K);
+  uint8_t *base = static_cast<uint8_t *>(ws);
+  uint8_t *qa = base + L.qa;
+  uint8_t *qb = base + L.qb;
+  float *sa = reinterpret_cast<float *>(base + L.sa);
+  float *sb = reinterpret_cast<float *>(base + L.sb);
+  uint32_t *amax = reinterpret_cast<uint32_t *>(base + L.amax);
+  if (M > 0) {
+    hipLaunchKernelGGL(fp8::quant_rows_kernel, dim3((unsigned)M), dim3(256), 0, s, (int)M, (int)K,
+                       L.Kp, A, lda, qa, sa);
+    if (gemm_status st = check_launch("quant_rows_kernel")) return st;
+  }
+  if (N > 0) {
+    const unsigned fg = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+    hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, N);
+    if (gemm_status st = check_launch("fill_u32_kernel")) return st;
+    const int krange = 128;
+    const unsigned ksplit = (unsigned)std::max<int64_t>(1, (K + krange - 1) / krange);
+    hipLaunchKernelGGL(fp8::col_amax_kernel, dim3((unsigned)((N + 255) / 256), ksplit), dim3(256),
+                       0, s, (int)K, (int)N, B, ldb, krange, amax);
+    if (gemm_status st = check_launch("col_amax_kernel")) return st;
+    hipLaunchKernelGGL(fp8::quant_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)((N + 63) / 64)),
+                       dim3(256), 0, s, (int)K, (int)N, L.Kp, B, ldb, amax, qb, sb);
+    if (gemm_status st = check_launch("quant_cols_t_kernel")) return st;
+  }
+  return GEMM_STATUS_OK;
+}
+
+gemm_status fp8_gemm_run(int64_t M, int64_t N, int64_t K, float alpha, const void *ws, float beta,
+                         float *C, int64_t ldc, hipStream_t s) {
+  const fp8::Layout L = fp8::layout(M, N, K);
+  const uint8_t *base = static_cast<const uint8_t *>(ws);
+  constexpr int BM = 256, BN = 256;
+  const int tiles_m = (int)((M + BM - 1) / BM), tiles_n = (int)((N + BN - 1) / BN);
+  const dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
+  const uint8_t *qa = base + L.qa, *qb = base + L.qb;
+  const float *sa = reinterpret_cast<const float *>(base + L.sa);
+  const float *sb = reinterpret_cast<const float *>(base + L.sb);
+  if (beta != 0.0f)
+    hipLaunchKernelGGL((fp8::gemm_fp8_kernel<BM, BN, 128, 128, true>), grid, block, 0, s, (int)M,
+                       (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((fp8::gemm_fp8_kernel<BM, BN, 128, 128, false>), grid, block, 0, s, (int)M,
+                       (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
+  return check_launch("gemm_fp8_kernel");
+}
+
+gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s) {
+  const int64_t want = (n + 255) / 256;
+  const unsigned grid = (unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+  hipLaunchKernelGGL(fp8::encode_kernel, dim3(grid), dim3(256), 0, s, n, x, out);
+  return check_launch("encode_kernel");
+}
+
+}  // namespace mm

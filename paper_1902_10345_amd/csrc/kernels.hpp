@@ -28,6 +28,24 @@ const TileConfig &f32_config(int i);
 int f32_default_config(int64_t M, int64_t N, int64_t K);
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s);
 
+// FP32-accurate split-precision path on bf16 MFMA.
+int bx3_num_configs();
+const TileConfig &bx3_config(int i);
+int bx3_config_products(int i);
+int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products);
+gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s);
+gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
+                      hipStream_t s);
+
+// Scaled FP8 path.
+size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K);
+int64_t fp8_kp(int64_t K);
+gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                             const float *B, int64_t ldb, void *ws, hipStream_t s);
+gemm_status fp8_gemm_run(int64_t M, int64_t N, int64_t K, float alpha, const void *ws, float beta,
+                         float *C, int64_t ldc, hipStream_t s);
+gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s);
+
 // C <- beta*C over an MxN block (alpha == 0 or K == 0 quick path).
 gemm_status scale_c(int64_t M, int64_t N, float beta, float *C, int64_t ldc, hipStream_t s);
 

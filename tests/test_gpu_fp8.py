@@ -1,0 +1,159 @@
+"""Scaled FP8 (OCP E4M3) path: the encoder and quantiser bit for bit against
+the oracle's, the matrix-core product against the dequantised-input oracle at
+binary32-accumulation level, and the end-to-end error against the exact
+product (the quantisation error itself)."""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from gpu_util import gamma, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def test_encoder_is_bitwise_the_oracle_encoder():
+    import torch
+    import paper_1902_10345_amd as mm
+    g = np.random.default_rng(8)
+    vals = np.array([oracle.e4m3_value(c) for c in range(127)], dtype=np.float64)
+    mids = (vals[:-1] + vals[1:]) / 2
+    x = np.concatenate([
+        g.uniform(-500, 500, 200000).astype(np.float32),
+        (g.standard_normal(200000) * 0.05).astype(np.float32),
+        (g.standard_normal(20000) * 1e-3).astype(np.float32),
+        vals.astype(np.float32), -vals.astype(np.float32),
+        mids.astype(np.float32), -mids.astype(np.float32),
+        np.nextafter(mids.astype(np.float32), np.float32(np.inf)),
+        np.nextafter(mids.astype(np.float32), np.float32(-np.inf)),
+        np.array([0.0, -0.0, 448.0, -448.0, 464.0, -464.0, 463.99, 1e30, -1e30, 1e-40, -1e-40,
+                  np.inf, -np.inf, np.nan], dtype=np.float32),
+    ]).astype(np.float32)
+    dx = torch.from_numpy(x).cuda()
+    codes = torch.empty(x.size, dtype=torch.uint8, device="cuda")
+    mm.fp8_e4m3_encode(x.size, dx, codes)
+    torch.cuda.synchronize()
+    got = codes.cpu().numpy()
+    ref = oracle.e4m3_encode(x)
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, [(float(x[i]), hex(got[i]), hex(ref[i])) for i in bad[:8]]
+
+
+def _quantize(mm, A, B, lda=None):
+    import torch
+    M, K = A.shape
+    _, N = B.shape
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dA = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    dB = torch.from_numpy(B).cuda()
+    mm.fp8_quantize(M, N, K, dA, K, dB, N, ws, nbytes)
+    torch.cuda.synchronize()
+    L = mm.fp8_workspace_layout(M, N, K)
+    h = ws.cpu().numpy()
+    Kp = L["Kp"]
+    qa = h[L["qa"]:L["qa"] + M * Kp].reshape(M, Kp)
+    qbT = h[L["qb"]:L["qb"] + N * Kp].reshape(N, Kp)
+    sa = h[L["sa"]:L["sa"] + 4 * M].view(np.float32)
+    sb = h[L["sb"]:L["sb"] + 4 * N].view(np.float32)
+    return ws, nbytes, qa, qbT, sa, sb, Kp
+
+
+@pytest.mark.parametrize("M,N,K,outliers", [(96, 80, 200, "none"), (257, 130, 1000, "A"),
+                                            (64, 300, 129, "B"), (1, 1, 1, "none")])
+def test_quantiser_is_bitwise_the_oracle(M, N, K, outliers):
+    import paper_1902_10345_amd as mm
+    A, B, _ = si.fp8_workload(M, N, K, seed=M + N + K, outliers=outliers)
+    A[0, :] = 0.0  # an all-zero row takes scale 1
+    _, _, qa, qbT, sa, sb, Kp = _quantize(mm, A, B)
+    rsa, rsb = oracle.fp8_scales_rows(A), oracle.fp8_scales_cols(B)
+    assert np.array_equal(sa, rsa) and np.array_equal(sb, rsb)
+    assert sa[0] == 1.0
+    assert np.array_equal(qa[:, :K], oracle.fp8_quantize_rows(A, rsa))
+    assert np.array_equal(qbT[:, :K].T, oracle.fp8_quantize_cols(B, rsb))
+    assert not qa[:, K:].any() and not qbT[:, K:].any()
+
+
+# The matrix core's internal summation of one 64-deep FP8 block is not
+# specified to IEEE sequential-rounding accuracy; componentwise errors of up to
+# 2.4 gamma_K against the dequantised oracle were measured, so the pin allows 8.
+FP8_MARGIN = 8
+
+
+def _dequant_bound(qa, sa, qbT, sb, K, alpha, beta, C0):
+    qa_abs = qa[:, :K] & 0x7F
+    qb_abs = np.ascontiguousarray(qbT[:, :K].T) & 0x7F
+    return oracle.gemm_fp8_dequant(qa_abs, sa, qb_abs, sb, alpha=abs(alpha), beta=abs(beta),
+                                   C0=None if C0 is None else np.abs(C0))
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 256), (300, 520, 130), (1, 77, 300), (130, 1, 64),
+                                   (513, 257, 1000), (64, 64, 1)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (1.5, 0.5)])
+def test_product_matches_dequantised_oracle(M, N, K, alpha, beta):
+    import torch
+    import paper_1902_10345_amd as mm
+    A, B, C0 = si.fp8_workload(M, N, K, seed=3 * M + N + K)
+    ws, nbytes, qa, qbT, sa, sb, Kp = _quantize(mm, A, B)
+    dC = torch.from_numpy(C0).cuda()
+    mm.gemm_fp8_prequantized(M, N, K, alpha, ws, nbytes, beta, dC, N)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy()
+    qb = np.ascontiguousarray(qbT[:, :K].T)
+    ref = oracle.gemm_fp8_dequant(qa[:, :K], sa, qb, sb, alpha=alpha, beta=beta, C0=C0)
+    den = _dequant_bound(qa, sa, qbT, sb, K, alpha, beta, C0)
+    cw = oracle.norms(C, ref, den)[3]
+    print("fp8 %dx%dx%d componentwise vs dequantised oracle: %.2f gamma_K" % (M, N, K, cw / gamma(K, extra=4)))
+    assert cw <= FP8_MARGIN * gamma(K, extra=4), cw
+
+
+@pytest.mark.parametrize("outliers", ["none", "A", "B"])
+def test_end_to_end_error_is_the_quantisation_error(outliers):
+    """gemm_fp8_scaled against the exact product: the relative Frobenius and
+    componentwise (|A||B|-relative) errors stay within the E4M3 quantisation
+    error (about 4e-2 and 4e-3..3e-2 for these inputs)."""
+    import torch
+    import paper_1902_10345_amd as mm
+    M, N, K = 256, 256, 1024
+    A, B, C0 = si.fp8_workload(M, N, K, seed=4, outliers=outliers)
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (A, B, C0))
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    mm.gemm_fp8_scaled(M, N, K, 1.5, dA, K, dB, N, 0.5, dC, N, ws, nbytes)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy()
+    ref = oracle.gemm(A, B, alpha=1.5, beta=0.5, C0=C0)
+    den = oracle.gemm_abs(A, B, alpha=1.5, beta=0.5, C0=C0)
+    rel, _, _, cw = oracle.norms(C, ref, den)
+    print("fp8 outliers=%s rel_fro=%.3e componentwise=%.3e" % (outliers, rel, cw))
+    assert rel <= 0.08
+    assert cw <= 0.08
+
+
+def test_full_size_sampled_rows():
+    """The 4096^3 workload with A-column outliers, in the launch the benchmark
+    times: sampled rows against the dequantised oracle and the exact one."""
+    import torch
+    import paper_1902_10345_amd as mm
+    M = N = K = 4096
+    A, B, C0 = si.fp8_workload(M, N, K, seed=4, outliers="A")
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (A, B, C0))
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    mm.gemm_fp8_scaled(M, N, K, 1.5, dA, K, dB, N, 0.5, dC, N, ws, nbytes)
+    torch.cuda.synchronize()
+    L = mm.fp8_workspace_layout(M, N, K)
+    h = ws.cpu().numpy()
+    Kp = L["Kp"]
+    rows = sample_rows(M, 16, 4)
+    qa = h[L["qa"]:L["qa"] + M * Kp].reshape(M, Kp)[rows, :K]
+    qb = np.ascontiguousarray(h[L["qb"]:L["qb"] + N * Kp].reshape(N, Kp)[:, :K].T)
+    sa = h[L["sa"]:L["sa"] + 4 * M].view(np.float32)[rows]
+    sb = h[L["sb"]:L["sb"] + 4 * N].view(np.float32)
+    C = dC.cpu().numpy()[rows]
+    ref = oracle.gemm_fp8_dequant(qa, sa, qb, sb, alpha=1.5, beta=0.5, C0=C0[rows])
+    den = oracle.gemm_fp8_dequant(qa & 0x7F, sa, qb & 0x7F, sb, alpha=1.5, beta=0.5,
+                                  C0=np.abs(C0[rows]))
+    assert oracle.norms(C, ref, den)[3] <= FP8_MARGIN * gamma(K, extra=4)
+    exact = oracle.gemm(A[rows], B, alpha=1.5, beta=0.5, C0=C0[rows])
+    assert oracle.rel_fro(C, exact) <= 0.08

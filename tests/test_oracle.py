@@ -186,6 +186,17 @@ def test_bf16_rne_matches_torch_conversion():
     assert np.array_equal(p0, ref)
 
 
+def test_bf16_split_last_plane_rounds_on_the_subnormal_grid():
+    # r1 - a1 = 9 * 2^-134 lies below bfloat16's subnormal spacing 2^-133, so
+    # the last plane rounds (9/2 -> 4, ties to even) to 2^-131.
+    x = np.array([float.fromhex('0x1.7512480000000p-113')], dtype=np.float32)
+    p0, p1, p2 = oracle.split_bf16x3(x)
+    assert float(p2[0]) == 2.0 ** -131
+    tiny = np.array([float.fromhex('0x1.8p-133')], dtype=np.float32)  # 3 * 2^-134
+    p0, p1, p2 = oracle.split_bf16x3(tiny)
+    assert float(p0[0]) == 2.0 ** -132 and float(p1[0]) == 0.0 and float(p2[0]) == 0.0
+
+
 def test_bf16_split_invariants():
     torch = pytest.importorskip("torch")
     x = np.concatenate([si.uniform((1, 100000), 72).ravel(),
