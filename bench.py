@@ -1,0 +1,269 @@
+"""Benchmark of the MI355X GEMM library (one GPU).
+
+Headline step: one FP32-accurate GEMM C <- 1.5*A*B + 0.5*C at M = N = K = 4096
+(binary32 row-major operands, uniform[-1,1), inputs resident in HBM) on the
+3xBF16 split-precision MFMA path.  The plain FP32 vector-ALU kernel, the
+6-product variant, the rectangular 8192x2048x4096 case, the scaled FP8 path,
+the grouped batch and the serving loop are measured beside it.
+
+Prints ONE JSON line.  Throughput counts 2*M*N*K algorithmic flops per GEMM
+(never padded tile work, never the extra split products).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --profile     # a few headline launches + a 1 GiB copy, for rocprofv3
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s).
+PEAK_BF16_MFMA = 2516.6
+PEAK_FP8_MFMA = 5033.2
+PEAK_FP32_VALU = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _dev_inputs(M, N, K, seed, torch):
+    import seeded_inputs as si
+    A = si.uniform((M, K), seed)
+    B = si.uniform((K, N), seed + 100)
+    C0 = si.uniform((M, N), seed + 200)
+    return (A, B, C0), tuple(torch.from_numpy(x).cuda() for x in (A, B, C0))
+
+
+def _time_steps(fn, steps, warmup, torch):
+    """Run `fn` warmup times, then time exactly `steps` calls on the current
+    stream.  Returns (ms_per_step from the block, per-step list in ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    block = ev[0].elapsed_time(ev[-1]) / steps
+    return block, per, wall
+
+
+def _stats(per):
+    """Median and a 95% confidence interval of the median (order statistics)
+    plus Tukey-fence outlier count, as in the paper's timing methodology."""
+    s = sorted(per)
+    n = len(s)
+    med = statistics.median(s)
+    # distribution-free CI for the median: ranks n/2 -+ 1.96 sqrt(n)/2
+    half = 1.96 * math.sqrt(n) / 2
+    lo = s[max(0, int(math.floor(n / 2 - half)))]
+    hi = s[min(n - 1, int(math.ceil(n / 2 + half)) - 1)]
+    q1, q3 = s[n // 4], s[(3 * n) // 4]
+    iqr = q3 - q1
+    out = sum(1 for v in s if v < q1 - 1.5 * iqr or v > q3 + 1.5 * iqr)
+    return {"median_ms": round(med, 5), "ci95_ms": [round(lo, 5), round(hi, 5)],
+            "tukey_outliers": out}
+
+
+def _traffic(kernel):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    calibrated against a copy of known size), read from profiles/; None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+    except Exception:
+        return None
+    if not rec:
+        return None
+    if rec.get("source_sha") != _source_sha(rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _source_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        p = os.path.join(ROOT, f)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def run_profile(torch, mm):
+    """Headline launches and a 1 GiB copy, for rocprofv3 counter runs."""
+    M = N = K = 4096
+    _, (A, B, C) = _dev_inputs(M, N, K, 2, torch)
+    for i in range(5):
+        mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, C, N, 3)
+        mm.gemm_f32(M, N, K, 1.5, A, K, B, N, 0.5, C, N)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    _log("profile run done: 5 x gemm_bx3, 5 x gemm_f32 (4096^3), 5 x copy of 1 GiB")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(sharding is a design note). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1902_10345_amd as mm
+    torch.cuda.set_device(0)
+    if args.profile:
+        run_profile(torch, mm)
+        return
+
+    K_, W_ = args.steps, args.warmup
+    paths = {}
+
+    # ---------------- headline: 4096^3 FP32-accurate on 3xBF16 MFMA --------
+    M = N = K = 4096
+    flops = 2.0 * M * N * K
+    (hA, hB, hC0), (A, B, C) = _dev_inputs(M, N, K, 2, torch)
+    _log("headline: gemm_f32_3xbf16 %dx%dx%d n_products=3" % (M, N, K))
+    ms, per, wall = _time_steps(
+        lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, C, N, 3), K_, W_, torch)
+    head_tflops = flops / (ms * 1e-3) / 1e12
+    paths["3xbf16_n3_4096^3"] = {"ms": round(ms, 4), "tflops": round(head_tflops, 1),
+                                "frac_bf16_peak": round(head_tflops / PEAK_BF16_MFMA, 4),
+                                "frac_3product_ceiling": round(head_tflops * 3 / PEAK_BF16_MFMA, 4),
+                                "frac_fp32_valu_peak": round(head_tflops / PEAK_FP32_VALU, 3),
+                                **_stats(per)}
+
+    # ---------------- the other paths --------------------------------------
+    def one(name, fn, fl, peak, peak_name):
+        _log("path: " + name)
+        ms_, per_, _ = _time_steps(fn, K_, W_, torch)
+        tf = fl / (ms_ * 1e-3) / 1e12
+        paths[name] = {"ms": round(ms_, 4), "tflops": round(tf, 1),
+                       "frac_" + peak_name: round(tf / peak, 4), **_stats(per_)}
+
+    Cf = C.clone()
+    one("f32_valu_4096^3", lambda: mm.gemm_f32(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N),
+        flops, PEAK_FP32_VALU, "fp32_valu_peak")
+    one("3xbf16_n6_4096^3", lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N, 6),
+        flops, PEAK_BF16_MFMA, "bf16_peak")
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    An = torch.randn(M, K, device="cuda")
+    Bn = torch.randn(K, N, device="cuda")
+    one("fp8_scaled_4096^3_with_quantize",
+        lambda: mm.gemm_fp8_scaled(M, N, K, 1.5, An, K, Bn, N, 0.5, Cf, N, ws, nbytes),
+        flops, PEAK_FP8_MFMA, "fp8_peak")
+    one("fp8_prequantized_4096^3",
+        lambda: mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, Cf, N),
+        flops, PEAK_FP8_MFMA, "fp8_peak")
+    del An, Bn, ws, Cf
+    M2, N2, K2 = 8192, 2048, 4096
+    _, (A2, B2, C2) = _dev_inputs(M2, N2, K2, 3, torch)
+    fl2 = 2.0 * M2 * N2 * K2
+    one("f32_valu_8192x2048x4096", lambda: mm.gemm_f32(M2, N2, K2, 1.5, A2, K2, B2, N2, 0.5, C2, N2),
+        fl2, PEAK_FP32_VALU, "fp32_valu_peak")
+    one("3xbf16_n3_8192x2048x4096",
+        lambda: mm.gemm_f32_3xbf16(M2, N2, K2, 1.5, A2, K2, B2, N2, 0.5, C2, N2, 3),
+        fl2, PEAK_BF16_MFMA, "bf16_peak")
+    del A2, B2, C2
+    M3 = 2048
+    _, (A3, B3, C3) = _dev_inputs(M3, M3, M3, 7, torch)
+    fl3 = 2.0 * M3 ** 3
+    one("f32_valu_2048^3", lambda: mm.gemm_f32(M3, M3, M3, 1.0, A3, M3, B3, M3, 0.0, C3, M3),
+        fl3, PEAK_FP32_VALU, "fp32_valu_peak")
+    one("3xbf16_n3_2048^3",
+        lambda: mm.gemm_f32_3xbf16(M3, M3, M3, 1.0, A3, M3, B3, M3, 0.0, C3, M3, 3),
+        fl3, PEAK_BF16_MFMA, "bf16_peak")
+    del A3, B3, C3
+    M4 = 256
+    _, (A4, B4, C4) = _dev_inputs(M4, M4, M4, 1, torch)
+    one("f32_valu_256^3", lambda: mm.gemm_f32(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4),
+        2.0 * M4 ** 3, PEAK_FP32_VALU, "fp32_valu_peak")
+
+    # ---------------- CPU baseline: the oracle on a bounded sample ----------
+    cpu = None
+    accuracy = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        # re-run the headline GEMM once from the original C0 for the accuracy check
+        Cchk = torch.from_numpy(hC0).cuda()
+        mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, Cchk, N, 3)
+        torch.cuda.synchronize()
+        # size the sample for about 15 s of CPU work from a 32-row probe
+        t0 = time.perf_counter()
+        oracle.gemm(hA[:32], hB, alpha=1.5, beta=0.5, C0=hC0[:32], nthreads=threads)
+        t32 = time.perf_counter() - t0
+        rows = int(min(M, max(32, 32 * 15.0 / max(t32, 1e-3))) // 32 * 32)
+        _log("cpu_baseline: oracle on %d rows of the 4096^3 product, %d threads" % (rows, threads))
+        sel = np.linspace(0, M - 1, rows).astype(np.int64)
+        t0 = time.perf_counter()
+        ref = oracle.gemm(hA[sel], hB, alpha=1.5, beta=0.5, C0=hC0[sel], nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(2.0 * rows * N * K / dt / 1e12, 6), "unit": "TFLOP/s",
+               "cores": threads, "kind": "oracle",
+               "sample": "%d of %d evenly spaced rows of the 4096^3 product (alpha=1.5, "
+                         "beta=0.5), FP64 i-k-j loop, %.1f s" % (rows, M, dt)}
+        accuracy = {"3xbf16_n3_rel_fro_sampled_rows": oracle.rel_fro(Cchk.cpu().numpy()[sel], ref)}
+
+    achieved = head_tflops
+    line = {
+        "metric": "FP32-accurate GEMM TFLOP/s & % peak: plain vs 3xBF16 MFMA; serve p50/p99 ms",
+        "value": round(head_tflops, 2),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": K_,
+        "warmup": W_,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "gemm 4096x4096x4096 fp32 row-major, alpha=1.5 beta=0.5, "
+                               "FP32-accurate via 3 bf16 split products on MFMA (fp32 accumulate)",
+                   "M": M, "N": N, "K": K, "path": "3xbf16", "n_products": 3,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_MFMA,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_MFMA, 4),
+                     "traffic": _traffic("gemm_bx3_kernel_4096")},
+        "cpu_baseline": cpu,
+        "paths": paths,
+        "accuracy": accuracy,
+        "wall_s_timed_region": round(wall, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,135 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
                             void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Grouped GEMM: many independent problems of uneven sizes in ONE persistent
+ * launch on the 3xBF16 path (3 products).  Workgroups dequeue output tiles
+ * from an atomic counter, the batch-dequeue mechanism the paper uses for
+ * consume scopes (Sec. 3.3), and each problem runs with its own tile shape.
+ *
+ * gemm_problem: one C <- alpha*A*B + beta*C with the conventions above
+ * (device pointers owned by the caller).  A problem with M == 0 or N == 0 is
+ * skipped; alpha == 0 or K == 0 gives C <- beta*C.
+ *
+ * tile_variant: per-problem tile shape (0: 128 x 128, 1: 64 x 64), or NULL
+ * for the library's choice (grouped_default_variant).  The autotuner
+ * (grouped_autotune) returns such an array.
+ *
+ * workspace: device memory of at least grouped_gemm_workspace_bytes(count)
+ * bytes, 256-byte aligned, owned by the caller; it holds the tile counter and
+ * the descriptor table.  Calls that share a workspace must not overlap.
+ *
+ * grouped_gemm uploads the descriptor table with a stream synchronisation
+ * (the host table is released on return) and then enqueues the launch.
+ * Arguments: 1 problems (host array), 2 count, 3 path (GEMM_PATH_3XBF16),
+ * 4 tile_variant (host array or NULL), 5 workspace, 6 ws_bytes, 7 stream.
+ *
+ * grouped_graph_create uploads the table once and captures the launch (a
+ * counter-clearing kernel and the persistent kernel, no memset nodes) into
+ * an executable HIP graph; grouped_graph_launch replays it on a stream with
+ * no host work; the workspace and the problems' buffers must stay valid until
+ * grouped_graph_destroy.  Arguments of create: 1..6 as grouped_gemm,
+ * 7 stream used for the upload, 8 graph (out).
+ * ---------------------------------------------------------------------- */
+typedef struct gemm_problem {
+  int64_t M, N, K, lda, ldb, ldc;
+  const float *A;
+  const float *B;
+  float *C;
+  float alpha, beta;
+} gemm_problem;
+
+size_t grouped_gemm_workspace_bytes(int count);
+int grouped_default_variant(int64_t M, int64_t N, int64_t K);
+gemm_status grouped_gemm(const gemm_problem *problems, int count, int path,
+                         const int *tile_variant, void *workspace, size_t ws_bytes,
+                         hipStream_t stream);
+gemm_status grouped_graph_create(const gemm_problem *problems, int count, int path,
+                                 const int *tile_variant, void *workspace, size_t ws_bytes,
+                                 hipStream_t stream, void **graph);
+gemm_status grouped_graph_launch(void *graph, hipStream_t stream);
+gemm_status grouped_graph_destroy(void *graph);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of GEMM requests on one GPU.
+ *
+ * A server owns a caller-provided device arena (the HBM operand budget; the
+ * memory stays owned by the caller, e.g. a torch tensor) and a scheduler
+ * thread.  Requests enter a FIFO; the head is admitted when a slot
+ * (max_slots requests in flight) and room in the arena are free, its operands
+ * are copied into the arena and it joins the next step: one grouped launch on
+ * the next idle stream of n_streams (default priority).  Steps on different
+ * streams overlap on the device, so requests that arrive while others run are
+ * admitted as slots and memory free up -- independent work on separate
+ * streams, as the paper maps connected components of a dataflow graph to
+ * concurrent GPU streams (Sec. 3.3, "Concurrency").  A request's tile shape
+ * depends only on its (M, N), so its result is bitwise the same alone and in
+ * any mix.  Host buffers should be pinned (hipHostMalloc, torch
+ * pin_memory) for asynchronous copies and must stay valid until the request
+ * completes; hC_out receives the MxN result.
+ *
+ * Latency = arrival (the caller's stamp on the server clock, or the submit
+ * time when arrival < 0) to the host observing the completion of the request's
+ * kernel; result latency additionally includes the copy of C to hC_out.
+ *
+ * server_create arguments: 1 arena (device, 256-byte aligned), 2 arena_bytes,
+ * 3 max_slots [1, 4096], 4 path (GEMM_PATH_3XBF16), 5 n_streams [1, 16],
+ * 6 out.  server_submit arguments: 1 server, 2 M, 3 N, 4 K, 5 alpha, 6 hA,
+ * 7 hB, 8 beta, 9 hC0 (read when beta != 0), 10 hC_out, 11 arrival (seconds on
+ * the server clock, or < 0), 12 ticket (out).  A request larger than the whole
+ * arena returns GEMM_STATUS_REJECTED.  server_poll returns GEMM_STATUS_NOT_READY
+ * until the result is in hC_out, then the latencies (and forgets the ticket).
+ * ---------------------------------------------------------------------- */
+typedef struct gemm_server gemm_server;
+gemm_status server_create(void *arena, size_t arena_bytes, int max_slots, int path,
+                          int n_streams, gemm_server **out);
+double server_now(gemm_server *server);
+gemm_status server_submit(gemm_server *server, int64_t M, int64_t N, int64_t K, float alpha,
+                          const float *hA, const float *hB, float beta, const float *hC0,
+                          float *hC_out, double arrival, uint64_t *ticket);
+gemm_status server_poll(gemm_server *server, uint64_t ticket, double *latency_ms,
+                        double *result_latency_ms);
+/* Blocks until every submitted request has completed (or timeout_s passes:
+ * GEMM_STATUS_NOT_READY). */
+gemm_status server_drain(gemm_server *server, double timeout_s);
+/* Latency percentiles over completed requests, throughput (completed
+ * algorithmic flops over first arrival .. last completion), counters. */
+gemm_status server_stats(gemm_server *server, double *p50_ms, double *p99_ms, double *tflops,
+                         uint64_t *completed, double *result_p50_ms, double *result_p99_ms,
+                         int *max_in_flight, size_t *arena_high_water, uint64_t *rejected);
+gemm_status server_destroy(gemm_server *server);
+
+/* ------------------------------------------------------------------------
+ * Autotuner: size-specific tuning of tile parameters (the paper tunes
+ * transformation parameters for a specific size, Sec. 6.2).
+ *
+ * gemm_autotune times every configuration of `path` (matching n_products on
+ * GEMM_PATH_3XBF16) on the caller's operands (C is overwritten), keeps the
+ * fastest for the size bucket of (M, N, K) (powers of two) and returns it;
+ * afterwards the entry points use the tuned choice for every shape in that
+ * bucket.  Arguments: 1 path, 2..12 as gemm_f32's 1..11, 13 n_products,
+ * 14 workspace, 15 ws_bytes (FP8), 16 reps, 17 stream, 18 best_cfg (out).
+ *
+ * grouped_autotune times candidate tile-shape policies for a grouped batch
+ * (all 128 x 128, all 64 x 64, and the padded-work rule at several costs of
+ * the small tile) and writes the fastest per-problem variants to
+ * variants_out (count ints); later library choices for grouped batches use
+ * the winning rule.  Arguments: 1 problems, 2 count, 3 path, 4 workspace,
+ * 5 ws_bytes, 6 reps, 7 stream, 8 variants_out.
+ *
+ * gemm_tuner_save / gemm_tuner_load write and read the tuned table as JSON.
+ * ---------------------------------------------------------------------- */
+gemm_status gemm_autotune(int path, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                          int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                          int64_t ldc, int n_products, void *workspace, size_t ws_bytes,
+                          int reps, hipStream_t stream, int *best_cfg);
+gemm_status grouped_autotune(const gemm_problem *problems, int count, int path, void *workspace,
+                             size_t ws_bytes, int reps, hipStream_t stream, int *variants_out);
+gemm_status gemm_tuner_save(const char *json_path);
+gemm_status gemm_tuner_load(const char *json_path);
+/* Forget every tuned choice (back to the library's default heuristics). */
+void gemm_tuner_clear(void);
+
+/* ------------------------------------------------------------------------
  * FP64 on-device error norm (verification only).
  * C (binary32, MxN, row stride ldc) against Cref (binary64, MxN dense); den
  * (binary64, MxN dense) may be NULL.  Writes four doubles to out (device):

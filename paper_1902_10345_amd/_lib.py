@@ -68,6 +68,38 @@ _sig("gemm_fp8_scaled", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32
 _sig("fp8_quantize", _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
 _sig("gemm_fp8_prequantized", _int, _i64, _i64, _i64, _f32, _vp, _sz, _f32, _vp, _i64, _vp)
 _sig("fp8_e4m3_encode", _int, _i64, _vp, _vp, _vp)
+
+
+class gemm_problem(ctypes.Structure):
+    _fields_ = [("M", _i64), ("N", _i64), ("K", _i64), ("lda", _i64), ("ldb", _i64),
+                ("ldc", _i64), ("A", _vp), ("B", _vp), ("C", _vp), ("alpha", _f32),
+                ("beta", _f32)]
+
+
+_PP = ctypes.POINTER(gemm_problem)
+_IP = ctypes.POINTER(_int)
+_sig("grouped_gemm_workspace_bytes", _sz, _int)
+_sig("grouped_default_variant", _int, _i64, _i64, _i64)
+_sig("grouped_gemm", _int, _PP, _int, _int, _IP, _vp, _sz, _vp)
+_sig("grouped_graph_create", _int, _PP, _int, _int, _IP, _vp, _sz, _vp, ctypes.POINTER(_vp))
+_sig("grouped_graph_launch", _int, _vp, _vp)
+_sig("grouped_graph_destroy", _int, _vp)
+_sig("server_create", _int, _vp, _sz, _int, _int, _int, ctypes.POINTER(_vp))
+_sig("server_now", _dbl, _vp)
+_sig("server_submit", _int, _vp, _i64, _i64, _i64, _f32, _vp, _vp, _f32, _vp, _vp, _dbl,
+     ctypes.POINTER(ctypes.c_uint64))
+_sig("server_poll", _int, _vp, ctypes.c_uint64, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl))
+_sig("server_drain", _int, _vp, _dbl)
+_sig("server_stats", _int, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
+     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
+     ctypes.POINTER(_int), ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_uint64))
+_sig("server_destroy", _int, _vp)
+_sig("gemm_autotune", _int, _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64,
+     _int, _vp, _sz, _int, _vp, ctypes.POINTER(_int))
+_sig("grouped_autotune", _int, _PP, _int, _int, _vp, _sz, _int, _vp, ctypes.POINTER(_int))
+_sig("gemm_tuner_save", _int, ctypes.c_char_p)
+_sig("gemm_tuner_load", _int, ctypes.c_char_p)
+_sig("gemm_tuner_clear", None)
 _sig("gemm_num_configs", _int, _int)
 _sig("gemm_config_name", ctypes.c_char_p, _int, _int)
 _sig("gemm_default_config", _int, _int, _i64, _i64, _i64)
@@ -169,6 +201,131 @@ def fp8_workspace_layout(M, N, K):
 
 
 PATH_F32, PATH_3XBF16, PATH_FP8 = 0, 1, 2
+
+
+def problem_array(problems):
+    """ctypes array of gemm_problem from tuples (M, N, K, A, lda, B, ldb, C, ldc,
+    alpha, beta), with A/B/C tensors or device addresses."""
+    arr = (gemm_problem * len(problems))()
+    for i, (M, N, K, A, lda, B, ldb, C, ldc, alpha, beta) in enumerate(problems):
+        arr[i] = gemm_problem(M, N, K, lda, ldb, ldc, ptr(A), ptr(B), ptr(C), alpha, beta)
+    return arr
+
+
+def _variants(tile_variant, count):
+    if tile_variant is None:
+        return None
+    v = (_int * count)(*[int(x) for x in tile_variant])
+    return v
+
+
+def server_create(arena, arena_bytes, max_slots, path, n_streams):
+    """Returns an opaque server handle (int)."""
+    h = _vp()
+    check(lib.server_create(ptr(arena), arena_bytes, max_slots, path, n_streams, ctypes.byref(h)))
+    return h.value
+
+
+def server_now(server) -> float:
+    return float(lib.server_now(server))
+
+
+def server_submit(server, M, N, K, alpha, hA, hB, beta, hC0, hC_out, arrival=-1.0) -> int:
+    t = ctypes.c_uint64()
+    check(lib.server_submit(server, M, N, K, alpha, ptr(hA), ptr(hB), beta, ptr(hC0), ptr(hC_out),
+                            arrival, ctypes.byref(t)))
+    return t.value
+
+
+def server_poll(server, ticket):
+    """None while in flight, else (latency_ms, result_latency_ms)."""
+    a, b = _dbl(), _dbl()
+    st = lib.server_poll(server, ticket, ctypes.byref(a), ctypes.byref(b))
+    if st == STATUS_NOT_READY:
+        return None
+    check(st)
+    return a.value, b.value
+
+
+def server_drain(server, timeout_s=60.0):
+    return check(lib.server_drain(server, timeout_s))
+
+
+def server_stats(server) -> dict:
+    p50, p99, tf, rp50, rp99 = _dbl(), _dbl(), _dbl(), _dbl(), _dbl()
+    done, rej = ctypes.c_uint64(), ctypes.c_uint64()
+    mif = _int()
+    hw = _sz()
+    check(lib.server_stats(server, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(tf),
+                           ctypes.byref(done), ctypes.byref(rp50), ctypes.byref(rp99),
+                           ctypes.byref(mif), ctypes.byref(hw), ctypes.byref(rej)))
+    return {"p50_ms": p50.value, "p99_ms": p99.value, "tflops": tf.value,
+            "completed": done.value, "result_p50_ms": rp50.value, "result_p99_ms": rp99.value,
+            "max_in_flight": mif.value, "arena_high_water_bytes": hw.value,
+            "rejected": rej.value}
+
+
+def server_destroy(server):
+    return check(lib.server_destroy(server))
+
+
+def gemm_autotune(path, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products=3,
+                  workspace=None, ws_bytes=0, reps=5, stream=None) -> int:
+    best = _int()
+    check(lib.gemm_autotune(path, M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
+                            n_products, ptr(workspace), ws_bytes, reps, stream_handle(stream),
+                            ctypes.byref(best)))
+    return best.value
+
+
+def grouped_autotune(problems, count, path, workspace, ws_bytes, reps=3, stream=None):
+    out = (_int * count)()
+    check(lib.grouped_autotune(problems, count, path, ptr(workspace), ws_bytes, reps,
+                               stream_handle(stream), out))
+    return list(out)
+
+
+def gemm_tuner_save(json_path):
+    return check(lib.gemm_tuner_save(json_path.encode()))
+
+
+def gemm_tuner_load(json_path):
+    return check(lib.gemm_tuner_load(json_path.encode()))
+
+
+def gemm_tuner_clear():
+    lib.gemm_tuner_clear()
+
+
+def grouped_gemm_workspace_bytes(count) -> int:
+    return int(lib.grouped_gemm_workspace_bytes(count))
+
+
+def grouped_default_variant(M, N, K) -> int:
+    return int(lib.grouped_default_variant(M, N, K))
+
+
+def grouped_gemm(problems, count, path, tile_variant, workspace, ws_bytes, stream=None):
+    """problems: a ctypes gemm_problem array (see problem_array)."""
+    return check(lib.grouped_gemm(problems, count, path, _variants(tile_variant, count),
+                                  ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def grouped_graph_create(problems, count, path, tile_variant, workspace, ws_bytes, stream=None):
+    """Returns an opaque graph handle (int)."""
+    h = _vp()
+    check(lib.grouped_graph_create(problems, count, path, _variants(tile_variant, count),
+                                   ptr(workspace), ws_bytes, stream_handle(stream),
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def grouped_graph_launch(graph, stream=None):
+    return check(lib.grouped_graph_launch(graph, stream_handle(stream)))
+
+
+def grouped_graph_destroy(graph):
+    return check(lib.grouped_graph_destroy(graph))
 
 
 def gemm_num_configs(path) -> int:

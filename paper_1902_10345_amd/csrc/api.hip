@@ -77,6 +77,16 @@ static gemm_status check_gemm_args(const char *fn, int64_t M, int64_t N, int64_t
   return GEMM_STATUS_OK;
 }
 
+static int pick_config(int path, int n_products, int64_t M, int64_t N, int64_t K) {
+  const int t = tuned_config(path, n_products, M, N, K);
+  if (t >= 0) return t;
+  switch (path) {
+    case GEMM_PATH_F32: return f32_default_config(M, N, K);
+    case GEMM_PATH_3XBF16: return bx3_default_config(M, N, K, n_products);
+    default: return 0;
+  }
+}
+
 }  // namespace mm
 
 using namespace mm;
@@ -96,7 +106,7 @@ gemm_status gemm_f32(int64_t M, int64_t N, int64_t K, float alpha, const float *
   if (st || ck.noop) return st;
   if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
   GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
-  return f32_run(g, f32_default_config(M, N, K), stream);
+  return f32_run(g, pick_config(GEMM_PATH_F32, 0, M, N, K), stream);
 }
 
 gemm_status gemm_f32_3xbf16(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
@@ -111,7 +121,7 @@ gemm_status gemm_f32_3xbf16(int64_t M, int64_t N, int64_t K, float alpha, const 
   if (ck.noop) return GEMM_STATUS_OK;
   if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
   GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
-  return bx3_run(g, bx3_default_config(M, N, K, n_products), stream);
+  return bx3_run(g, pick_config(GEMM_PATH_3XBF16, n_products, M, N, K), stream);
 }
 
 gemm_status split_bf16x3(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
@@ -219,12 +229,8 @@ const char *gemm_config_name(int path, int cfg) {
 }
 
 int gemm_default_config(int path, int64_t M, int64_t N, int64_t K) {
-  switch (path) {
-    case GEMM_PATH_F32: return f32_default_config(M, N, K);
-    case GEMM_PATH_3XBF16: return bx3_default_config(M, N, K, 3);
-    case GEMM_PATH_FP8: return 0;
-    default: return -1;
-  }
+  if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8) return -1;
+  return pick_config(path, 3, M, N, K);
 }
 
 gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, float alpha,
@@ -254,9 +260,7 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
     return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
   }
   GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
-  if (cfg < 0)
-    cfg = path == GEMM_PATH_3XBF16 ? bx3_default_config(M, N, K, n_products)
-                                   : gemm_default_config(path, M, N, K);
+  if (cfg < 0) cfg = pick_config(path, n_products, M, N, K);
   switch (path) {
     case GEMM_PATH_F32: return f32_run(g, cfg, stream);
     case GEMM_PATH_3XBF16: return bx3_run(g, cfg, stream);

@@ -70,6 +70,7 @@ static const Bx3Config kBx3Configs[] = {
     {{256, 256, 32, "bx3_256x256x32_4w128x128_p3"}, 2},
     {{256, 256, 16, "bx3_256x256x16_8w128x64_p6"}, 3},
     {{128, 128, 32, "bx3_128x128x32_4w64x64_p6"}, 3},
+    {{64, 64, 32, "bx3_64x64x32_4w32x32_p3"}, 2},
 };
 
 int bx3_num_configs() { return (int)(sizeof(kBx3Configs) / sizeof(kBx3Configs[0])); }
@@ -84,7 +85,9 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   if (big >= cus) return 0;
   const int64_t mid = ((M + 255) / 256) * ((N + 127) / 128);
   if (mid >= cus) return 2;
-  return 1;
+  const int64_t small = ((M + 127) / 128) * ((N + 127) / 128);
+  if (small >= cus / 2) return 1;
+  return 6;
 }
 
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
@@ -95,6 +98,7 @@ gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 3: return bx3::launch<256, 256, 32, 128, 128, 2, 4>(g, s);
     case 4: return bx3::launch<256, 256, 16, 128, 64, 3, 8>(g, s);
     case 5: return bx3::launch<128, 128, 32, 64, 64, 3, 4>(g, s);
+    case 6: return bx3::launch<64, 64, 32, 32, 32, 2, 4>(g, s);
     default: set_error("gemm_f32_3xbf16: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

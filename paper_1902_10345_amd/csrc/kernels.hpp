@@ -46,6 +46,10 @@ gemm_status fp8_gemm_run(int64_t M, int64_t N, int64_t K, float alpha, const voi
                          float *C, int64_t ldc, hipStream_t s);
 gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s);
 
+// Autotuner table: the tuned configuration for this size bucket, or -1.
+int tuned_config(int path, int n_products, int64_t M, int64_t N, int64_t K);
+double tuned_small_cost();
+
 // C <- beta*C over an MxN block (alpha == 0 or K == 0 quick path).
 gemm_status scale_c(int64_t M, int64_t N, float beta, float *C, int64_t ldc, hipStream_t s);
 

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import seeded_inputs as si
-from gpu_util import dev_matrix, gamma, sample_rows
+from gpu_util import check_split_result, dev_matrix, sample_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -45,19 +45,7 @@ def _run(mm, M, N, K, alpha, beta, n, seed, cfg=None, lds=(None, None, None)):
 
 
 def _check(A, B, C0, C, alpha, beta, n):
-    """Two pins: (1) against the exact product, relative Frobenius <= 1e-5;
-    (2) against the exact sum of the selected split products, componentwise
-    within binary32 accumulation of n*K terms (with a factor 2 margin for the
-    matrix core's internal summation)."""
-    K = A.shape[1]
-    ref = oracle.gemm(A, B, alpha=alpha, beta=beta, C0=C0)
-    rel = oracle.rel_fro(C, ref)
-    assert rel <= 1e-5, rel
-    split = oracle.gemm_bf16_split(A, B, n, alpha=alpha, beta=beta, C0=C0)
-    den = oracle.gemm_abs(A, B, alpha=alpha, beta=beta, C0=C0)
-    cw = oracle.norms(C, split, den)[3]
-    assert cw <= 2 * 1.01 * gamma(n * K), (cw, gamma(n * K))
-    return rel
+    return check_split_result(oracle, A, B, C0, C, alpha, beta, n)
 
 
 def test_staging_split_is_bitwise_the_oracle_split():
