@@ -1,0 +1,168 @@
+"""Host-side logic that needs no GPU: the autotuner's JSON cache, workspace
+layouts, tile-shape heuristics, argument checks of the grouped / FP8 /
+serving entry points, and the seeded workload generators."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+
+F = 16  # non-null dummy device address; never dereferenced on rejection
+
+
+def test_tuner_json_round_trip(tmp_path):
+    import paper_1902_10345_amd as mm
+    src = tmp_path / "in.json"
+    name = mm.gemm_config_name(mm.PATH_3XBF16, 1)
+    src.write_text(
+        '{"arch": "gfx950", "grouped_small_cost": 2.5, "entries": [\n'
+        '{"path": 1, "n_products": 3, "log2_m": 12, "log2_n": 12, "log2_k": 12, "config": "%s"},\n'
+        '{"path": 1, "n_products": 3, "log2_m": 5, "log2_n": 5, "log2_k": 5, "config": "no_such_config"}\n'
+        ']}\n' % name)
+    mm.gemm_tuner_load(str(src))
+    try:
+        # the tuned choice replaces the heuristic for every shape in the bucket
+        assert mm.gemm_default_config(mm.PATH_3XBF16, 4096, 4000, 3000) == 1
+        out = tmp_path / "out.json"
+        mm.gemm_tuner_save(str(out))
+        doc = json.loads(out.read_text())
+        assert doc["grouped_small_cost"] == 2.5
+        assert doc["entries"] == [{"path": 1, "n_products": 3, "log2_m": 12, "log2_n": 12,
+                                   "log2_k": 12, "config": name}]
+    finally:
+        mm.gemm_tuner_clear()
+    assert mm.gemm_default_config(mm.PATH_3XBF16, 4096, 4096, 4096) != -1
+
+
+def test_tuner_load_missing_file_is_an_error():
+    import paper_1902_10345_amd as mm
+    with pytest.raises(mm.GemmError):
+        mm.gemm_tuner_load("/nonexistent/dir/tuner.json")
+
+
+def test_fp8_workspace_layout_matches_library():
+    import paper_1902_10345_amd as mm
+    for (M, N, K) in [(1, 1, 1), (4096, 4096, 4096), (300, 77, 129), (8, 3000, 1000)]:
+        L = mm.fp8_workspace_layout(M, N, K)
+        total = mm.gemm_fp8_workspace_bytes(M, N, K)
+        assert L["Kp"] % 128 == 0 and L["Kp"] >= K
+        assert L["qb"] >= M * L["Kp"] and L["sa"] >= L["qb"] + N * L["Kp"]
+        assert all(L[k] % 256 == 0 for k in ("qa", "qb", "sa", "sb"))
+        assert total >= L["sb"] + 4 * N
+
+
+def test_grouped_workspace_and_variant_heuristic():
+    import paper_1902_10345_amd as mm
+    assert mm.grouped_gemm_workspace_bytes(0) >= 256
+    assert mm.grouped_gemm_workspace_bytes(512) >= 512 * 80 + 513 * 4
+    # small problems take the 64 x 64 tile, large ones the 128 x 128 tile
+    assert mm.grouped_default_variant(32, 32, 100) == 1
+    assert mm.grouped_default_variant(1024, 1024, 100) == 0
+    assert mm.grouped_default_variant(48, 1024, 100) == 1   # half the 128-row tile wasted
+
+
+def test_default_configs_are_valid_indices():
+    import paper_1902_10345_amd as mm
+    for path in (mm.PATH_F32, mm.PATH_3XBF16):
+        n = mm.gemm_num_configs(path)
+        for shape in [(256, 256, 256), (4096, 4096, 4096), (8192, 2048, 4096), (17, 5000, 3)]:
+            c = mm.gemm_default_config(path, *shape)
+            assert 0 <= c < n, (path, shape, c)
+
+
+def test_grouped_argument_codes():
+    import paper_1902_10345_amd as mm
+    ws_bytes = mm.grouped_gemm_workspace_bytes(2)
+    good = (64, 64, 64, F, 64, F, 64, F, 64, 1.0, 0.0)
+    arr = mm.problem_array([good, good])
+    lib = mm.lib
+    assert lib.grouped_gemm(arr, -1, mm.PATH_3XBF16, None, F, ws_bytes, None) == -2
+    assert lib.grouped_gemm(None, 2, mm.PATH_3XBF16, None, F, ws_bytes, None) == -1
+    assert lib.grouped_gemm(arr, 2, mm.PATH_F32, None, F, ws_bytes, None) == -3
+    assert lib.grouped_gemm(arr, 2, mm.PATH_3XBF16, None, None, ws_bytes, None) == -5
+    assert lib.grouped_gemm(arr, 2, mm.PATH_3XBF16, None, 256, ws_bytes - 1, None) == -6
+    assert lib.grouped_gemm(arr, 2, mm.PATH_3XBF16, None, 8, ws_bytes, None) == -5  # unaligned
+    bad = mm.problem_array([good, (64, 64, 64, F, 63, F, 64, F, 64, 1.0, 0.0)])
+    assert lib.grouped_gemm(bad, 2, mm.PATH_3XBF16, None, 256, ws_bytes, None) == -1
+    assert "problems[1]" in mm.last_error()
+    import ctypes
+    v = (ctypes.c_int * 2)(0, 7)
+    assert lib.grouped_gemm(arr, 2, mm.PATH_3XBF16, v, 256, ws_bytes, None) == -4
+
+
+def test_fp8_argument_codes():
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    nb = mm.gemm_fp8_workspace_bytes(64, 64, 64)
+    args = (64, 64, 64, 1.0, F, 64, F, 64, 0.0, F, 64)
+    assert lib.gemm_fp8_scaled(*args, None, nb, None) == -12
+    assert lib.gemm_fp8_scaled(*args, 256, nb - 1, None) == -13
+    assert lib.gemm_fp8_scaled(*args, 8, nb, None) == -12
+    assert lib.fp8_quantize(64, 64, 64, F, 63, F, 64, 256, nb, None) == -5
+    assert lib.gemm_fp8_prequantized(64, 64, 64, 1.0, 256, nb, 0.0, F, 63, None) == -9
+    assert lib.fp8_e4m3_encode(-1, F, F, None) == -1
+    assert lib.split_bf16x3(-1, F, F, F, None, None) == -1
+    # the split and encoder accept n == 0 without touching the device
+    assert lib.split_bf16x3(0, None, None, None, None, None) == 0
+
+
+def test_3xbf16_argument_codes():
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    assert lib.gemm_f32_3xbf16(4, 4, 4, 1.0, F, 4, F, 4, 0.0, F, 4, 5, None) == -12
+    assert lib.gemm_f32_3xbf16(4, 4, 4, 1.0, F, 3, F, 4, 0.0, F, 4, 3, None) == -6
+    assert lib.gemm_f32_3xbf16(0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 3, None) == 0
+
+
+def test_server_argument_codes():
+    import ctypes
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    out = ctypes.c_void_p()
+    assert lib.server_create(None, 1 << 20, 8, mm.PATH_3XBF16, 2, ctypes.byref(out)) == -1
+    assert lib.server_create(8, 1 << 20, 8, mm.PATH_3XBF16, 2, ctypes.byref(out)) == -1
+    assert lib.server_create(256, 1 << 20, 0, mm.PATH_3XBF16, 2, ctypes.byref(out)) == -3
+    assert lib.server_create(256, 1 << 20, 8, mm.PATH_F32, 2, ctypes.byref(out)) == -4
+    assert lib.server_create(256, 1 << 20, 8, mm.PATH_3XBF16, 0, ctypes.byref(out)) == -5
+    assert lib.server_create(256, 1024, 8, mm.PATH_3XBF16, 2, ctypes.byref(out)) == -2
+    t = ctypes.c_uint64()
+    assert lib.server_submit(None, 1, 1, 1, 1.0, F, F, 0.0, None, F, -1.0, ctypes.byref(t)) == -1
+
+
+# ------------------------------------------------------------- generators ---
+
+def test_log_uniform_sizes_are_in_range_and_rounded():
+    s = si.log_uniform_sizes(5000, 32, 1024, seed=5, multiple=16)
+    assert s.min() >= 32 and s.max() <= 1024 and np.all(s % 16 == 0)
+    # log-uniform: the median of exp(U[ln 32, ln 1024]) is sqrt(32*1024) = 181
+    assert abs(np.median(s) - math.sqrt(32 * 1024)) < 20
+    r = si.log_uniform_sizes(5000, 64, 2048, seed=6, multiple=1)
+    assert r.min() >= 64 and r.max() <= 2048 and np.any(r % 16 != 0)
+
+
+def test_poisson_arrivals_rate():
+    t = si.poisson_arrivals(2000.0, 10.0, seed=6)
+    assert np.all(np.diff(t) >= 0) and t[-1] < 10.0
+    assert abs(len(t) - 20000) < 5 * math.sqrt(20000)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 1 / 2000.0) < 0.05 / 2000.0
+
+
+def test_fp8_workload_outliers():
+    A, B, C0 = si.fp8_workload(64, 200, 300, seed=4, outliers="A")
+    big = np.abs(A).max(axis=0) > 100
+    assert big.sum() == math.ceil(0.01 * 300)
+    A2, B2, _ = si.fp8_workload(64, 200, 300, seed=4, outliers="B")
+    assert (np.abs(B2).max(axis=0) > 100).sum() == math.ceil(0.01 * 200)
+
+
+def test_uniform_is_seeded_and_in_range():
+    a = si.uniform((100, 100), 3)
+    b = si.uniform((100, 100), 3)
+    assert np.array_equal(a, b) and a.dtype == np.float32
+    assert a.min() >= -1.0 and a.max() < 1.0
+    p = si.uniform((10, 7), 3, ld=9, pad_value=np.nan)
+    assert p.shape == (10, 7) and p.strides[0] == 9 * 4
