@@ -110,6 +110,113 @@ def _source_sha(files):
     return h.hexdigest()[:16]
 
 
+def run_grouped(torch, mm, steps, warmup):
+    """512 problems, M, N, K log-uniform in [32, 1024] (multiples of 16), one
+    persistent launch captured in a HIP graph, tile shapes from the autotuner."""
+    import numpy as np
+    import seeded_inputs as si
+    probs = si.grouped_problems(512, seed=5)
+    dev, flops, min_bytes = [], 0.0, 0.0
+    for (M, N, K, A, B) in probs:
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
+        dev.append((M, N, K, dA, K, dB, N, dC, N, 1.0, 0.0))
+        flops += 2.0 * M * N * K
+        min_bytes += 4.0 * (M * K + K * N + M * N)
+    arr = mm.problem_array(dev)
+    ws_bytes = mm.grouped_gemm_workspace_bytes(len(dev))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    variants = mm.grouped_autotune(arr, len(dev), mm.PATH_3XBF16, ws, ws_bytes, reps=3)
+    g = mm.grouped_graph_create(arr, len(dev), mm.PATH_3XBF16, variants, ws, ws_bytes)
+    try:
+        ms, per, _ = _time_steps(lambda: mm.grouped_graph_launch(g), steps, warmup, torch)
+    finally:
+        mm.grouped_graph_destroy(g)
+    tf = flops / (ms * 1e-3) / 1e12
+    gbs = min_bytes / (ms * 1e-3) / 1e9
+    n128 = int(sum(1 for v in variants if v == 0))
+    return {"problems": len(dev), "gflop": round(flops / 1e9, 3),
+            "min_hbm_mb": round(min_bytes / 1e6, 1), "ms": round(ms, 4),
+            "tflops": round(tf, 1), "frac_3product_ceiling": round(tf * 3 / PEAK_BF16_MFMA, 4),
+            "hbm_gbs_of_min_bytes": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+            "tiles_128x128": n128, "tiles_64x64": len(dev) - n128,
+            "launch": "hipGraph replay (counter clear + persistent kernel)", **_stats(per)}
+
+
+def run_serving(torch, mm, seconds, rate=2000.0):
+    """Poisson arrivals at `rate` req/s for `seconds`; each request an
+    FP32-accurate GEMM with M, N, K log-uniform in [64, 2048]; admission by a
+    16 GB HBM operand budget; operands from a pinned host pool."""
+    import collections
+    import seeded_inputs as si
+    t_arr, sizes = si.serving_requests(rate, seconds, seed=6)
+    pool_n = 1 << 26                                 # 256 MB of uniform values
+    pool = torch.from_numpy(si.uniform((1, pool_n), 61).reshape(-1)).pin_memory()
+    ring_n = 1 << 27                                 # 512 MB pinned output ring
+    ring = torch.empty(ring_n, dtype=torch.float32, pin_memory=True)
+    budget = 16 << 30
+    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    srv = mm.server_create(arena, budget, 1024, mm.PATH_3XBF16, 4)
+    outstanding = collections.deque()                 # (ticket, ring_off, n)
+    head = 0
+    lat = []
+
+    def reap():
+        """Collect completed requests in submission order."""
+        while outstanding:
+            r = mm.server_poll(srv, outstanding[0][0])
+            if r is None:
+                return
+            lat.append(r)
+            outstanding.popleft()
+
+    def overlaps_oldest(lo, hi):
+        return bool(outstanding) and outstanding[0][1] < hi and outstanding[0][1] + outstanding[0][2] > lo
+
+    try:
+        time.sleep(0.05)
+        base = mm.server_now(srv) + 0.05
+        for i, (ta, (M, N, K)) in enumerate(zip(t_arr, sizes)):
+            M, N, K = int(M), int(N), int(K)
+            due = base + float(ta)
+            while mm.server_now(srv) < due:
+                pass
+            n = M * N
+            if head + n > ring_n:
+                head = 0
+            # ring slots are reused in order: wait for the oldest result that
+            # still occupies [head, head + n)
+            while overlaps_oldest(head, head + n):
+                reap()
+                if overlaps_oldest(head, head + n):
+                    time.sleep(20e-6)
+            offA = (i * 2654435761) % (pool_n - M * K)
+            offB = (i * 40503 + 12345) % (pool_n - K * N)
+            hA = pool[offA:offA + M * K]
+            hB = pool[offB:offB + K * N]
+            hC = ring[head:head + n]
+            t = mm.server_submit(srv, M, N, K, 1.0, hA, hB, 0.0, None, hC, due)
+            outstanding.append((t, head, n))
+            head += n
+            if i % 8 == 0:
+                reap()
+        mm.server_drain(srv, 120.0)
+        reap()
+        st = mm.server_stats(srv)
+    finally:
+        mm.server_destroy(srv)
+    del arena
+    offered = sum(2.0 * float(m) * float(n_) * float(k) for (m, n_, k) in sizes) / seconds
+    return {"rate_req_s": rate, "seconds": seconds, "requests": int(len(t_arr)),
+            "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
+            "result_p50_ms": round(st["result_p50_ms"], 4),
+            "result_p99_ms": round(st["result_p99_ms"], 4),
+            "tflops": round(st["tflops"], 3), "offered_tflops": round(offered / 1e12, 3),
+            "completed": st["completed"], "max_in_flight": st["max_in_flight"],
+            "arena_high_water_mb": round(st["arena_high_water_bytes"] / 1e6, 1),
+            "budget_gb": budget / (1 << 30), "streams": 4, "slots": 1024}
+
+
 def run_profile(torch, mm):
     """Headline launches and a 1 GiB copy, for rocprofv3 counter runs."""
     M = N = K = 4096
@@ -132,6 +239,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline GEMM (for kernel-trace profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -162,6 +274,9 @@ def main():
                                 "frac_fp32_valu_peak": round(head_tflops / PEAK_FP32_VALU, 3),
                                 **_stats(per)}
 
+    if args.headline_only:
+        args.no_grouped = args.no_serving = args.no_cpu_baseline = True
+
     # ---------------- the other paths --------------------------------------
     def one(name, fn, fl, peak, peak_name):
         _log("path: " + name)
@@ -170,44 +285,54 @@ def main():
         paths[name] = {"ms": round(ms_, 4), "tflops": round(tf, 1),
                        "frac_" + peak_name: round(tf / peak, 4), **_stats(per_)}
 
-    Cf = C.clone()
-    one("f32_valu_4096^3", lambda: mm.gemm_f32(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N),
-        flops, PEAK_FP32_VALU, "fp32_valu_peak")
-    one("3xbf16_n6_4096^3", lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N, 6),
-        flops, PEAK_BF16_MFMA, "bf16_peak")
-    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    An = torch.randn(M, K, device="cuda")
-    Bn = torch.randn(K, N, device="cuda")
-    one("fp8_scaled_4096^3_with_quantize",
-        lambda: mm.gemm_fp8_scaled(M, N, K, 1.5, An, K, Bn, N, 0.5, Cf, N, ws, nbytes),
-        flops, PEAK_FP8_MFMA, "fp8_peak")
-    one("fp8_prequantized_4096^3",
-        lambda: mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, Cf, N),
-        flops, PEAK_FP8_MFMA, "fp8_peak")
-    del An, Bn, ws, Cf
-    M2, N2, K2 = 8192, 2048, 4096
-    _, (A2, B2, C2) = _dev_inputs(M2, N2, K2, 3, torch)
-    fl2 = 2.0 * M2 * N2 * K2
-    one("f32_valu_8192x2048x4096", lambda: mm.gemm_f32(M2, N2, K2, 1.5, A2, K2, B2, N2, 0.5, C2, N2),
-        fl2, PEAK_FP32_VALU, "fp32_valu_peak")
-    one("3xbf16_n3_8192x2048x4096",
-        lambda: mm.gemm_f32_3xbf16(M2, N2, K2, 1.5, A2, K2, B2, N2, 0.5, C2, N2, 3),
-        fl2, PEAK_BF16_MFMA, "bf16_peak")
-    del A2, B2, C2
-    M3 = 2048
-    _, (A3, B3, C3) = _dev_inputs(M3, M3, M3, 7, torch)
-    fl3 = 2.0 * M3 ** 3
-    one("f32_valu_2048^3", lambda: mm.gemm_f32(M3, M3, M3, 1.0, A3, M3, B3, M3, 0.0, C3, M3),
-        fl3, PEAK_FP32_VALU, "fp32_valu_peak")
-    one("3xbf16_n3_2048^3",
-        lambda: mm.gemm_f32_3xbf16(M3, M3, M3, 1.0, A3, M3, B3, M3, 0.0, C3, M3, 3),
-        fl3, PEAK_BF16_MFMA, "bf16_peak")
-    del A3, B3, C3
-    M4 = 256
-    _, (A4, B4, C4) = _dev_inputs(M4, M4, M4, 1, torch)
-    one("f32_valu_256^3", lambda: mm.gemm_f32(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4),
-        2.0 * M4 ** 3, PEAK_FP32_VALU, "fp32_valu_peak")
+    if not args.headline_only:
+        Cf = C.clone()
+        one("f32_valu_4096^3", lambda: mm.gemm_f32(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N),
+            flops, PEAK_FP32_VALU, "fp32_valu_peak")
+        one("3xbf16_n6_4096^3", lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N, 6),
+            flops, PEAK_BF16_MFMA, "bf16_peak")
+        nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        An = torch.randn(M, K, device="cuda")
+        Bn = torch.randn(K, N, device="cuda")
+        one("fp8_scaled_4096^3_with_quantize",
+            lambda: mm.gemm_fp8_scaled(M, N, K, 1.5, An, K, Bn, N, 0.5, Cf, N, ws, nbytes),
+            flops, PEAK_FP8_MFMA, "fp8_peak")
+        one("fp8_prequantized_4096^3",
+            lambda: mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, Cf, N),
+            flops, PEAK_FP8_MFMA, "fp8_peak")
+        del An, Bn, ws, Cf
+        M2, N2, K2 = 8192, 2048, 4096
+        _, (A2, B2, C2) = _dev_inputs(M2, N2, K2, 3, torch)
+        fl2 = 2.0 * M2 * N2 * K2
+        one("f32_valu_8192x2048x4096", lambda: mm.gemm_f32(M2, N2, K2, 1.5, A2, K2, B2, N2, 0.5, C2, N2),
+            fl2, PEAK_FP32_VALU, "fp32_valu_peak")
+        one("3xbf16_n3_8192x2048x4096",
+            lambda: mm.gemm_f32_3xbf16(M2, N2, K2, 1.5, A2, K2, B2, N2, 0.5, C2, N2, 3),
+            fl2, PEAK_BF16_MFMA, "bf16_peak")
+        del A2, B2, C2
+        M3 = 2048
+        _, (A3, B3, C3) = _dev_inputs(M3, M3, M3, 7, torch)
+        fl3 = 2.0 * M3 ** 3
+        one("f32_valu_2048^3", lambda: mm.gemm_f32(M3, M3, M3, 1.0, A3, M3, B3, M3, 0.0, C3, M3),
+            fl3, PEAK_FP32_VALU, "fp32_valu_peak")
+        one("3xbf16_n3_2048^3",
+            lambda: mm.gemm_f32_3xbf16(M3, M3, M3, 1.0, A3, M3, B3, M3, 0.0, C3, M3, 3),
+            fl3, PEAK_BF16_MFMA, "bf16_peak")
+        del A3, B3, C3
+        M4 = 256
+        _, (A4, B4, C4) = _dev_inputs(M4, M4, M4, 1, torch)
+        one("f32_valu_256^3", lambda: mm.gemm_f32(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4),
+            2.0 * M4 ** 3, PEAK_FP32_VALU, "fp32_valu_peak")
+
+    grouped = None
+    if not args.no_grouped:
+        _log("grouped: 512 problems, autotuned tiles, graph replay")
+        grouped = run_grouped(torch, mm, K_, W_)
+    serving = None
+    if not args.no_serving:
+        _log("serving: Poisson 2000 req/s for %.0f s" % args.serve_seconds)
+        serving = run_serving(torch, mm, args.serve_seconds)
 
     # ---------------- CPU baseline: the oracle on a bounded sample ----------
     cpu = None
@@ -259,6 +384,8 @@ def main():
                      "traffic": _traffic("gemm_bx3_kernel_4096")},
         "cpu_baseline": cpu,
         "paths": paths,
+        "grouped": grouped,
+        "serving": serving,
         "accuracy": accuracy,
         "wall_s_timed_region": round(wall, 3),
     }

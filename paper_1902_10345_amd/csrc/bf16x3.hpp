@@ -11,9 +11,10 @@
 //   MapTiling       BM x BN workgroup tile over (i, j); 2 x 2 waves, each a
 //                   WM x WN wave tile of 32 x 32 MFMA blocks; K in BK slabs.
 //   LocalStorage    A slab as [plane][BM][BK] and B slab transposed as
-//   DoubleBuffering [plane][BN][BK] bf16 in LDS, two stages; the slab t+1
-//                   global loads are issued before slab t is multiplied and
-//                   its split/stores are interleaved with slab t's MFMAs.
+//   DoubleBuffering [plane][BN][BK] bf16 in LDS, two stages, plus two register
+//                   sets for the global loads: while slab t is multiplied,
+//                   slab t+2 is in flight from HBM and slab t+1 is split and
+//                   written to the other LDS stage.
 //   Vectorization   128-bit global loads of A rows, 128-bit LDS writes and
 //                   ds_read_b128 fragment reads.
 //   ReducePeeling   alpha/beta applied once in the epilogue.
@@ -22,6 +23,8 @@
 // fall in distinct banks (for both 32- and 64-bank LDS organisations).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -29,6 +32,12 @@ namespace mm {
 namespace bx3 {
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Word 3 of a raw buffer resource on gfx9-class GPUs: 32-bit data format,
+// no swizzle; the hardware range check returns zero for reads past
+// num_records.
+constexpr int kBufferFlags = 0x00020000;
 
 // Round-to-nearest-even split of a binary32 value into bfloat16 planes.
 __device__ __forceinline__ void split2(float x, __bf16 &h, __bf16 &l) {
@@ -87,63 +96,80 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   const int lane = tid & 63, wave = tid >> 6;
   const int Mr = M - m0, Nr = N - n0;
   const bool interior = Mr >= BM && Nr >= BN;
-  const float *Ab = A + (int64_t)m0 * lda;
-  const float *Bb = B + n0;
-  // 32-bit element offsets of this lane's A items inside the tile's row panel
-  // (the launcher guarantees BM * lda + K < 2^31).
-  int a_off[G::A_ITEMS];
+  // Staging loads are raw buffer loads: the resource holds the tile's base
+  // address and the number of valid bytes, so reads past the matrix return
+  // zero in hardware and lane addresses stay 32-bit offsets (no 64-bit VALU
+  // address arithmetic).  The launcher guarantees (BM * lda + K) * 4 < 2^31.
+  const int rowsA = Mr < BM ? Mr : BM;
+  const __amdgpu_buffer_rsrc_t rsrcA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(A + (int64_t)m0 * lda), (short)0,
+      rowsA > 0 ? (int)(((int64_t)(rowsA - 1) * lda + K) * 4) : 0, kBufferFlags);
+  const int colsB = Nr < BN ? Nr : BN;
+  // byte offsets of this lane's A items inside the tile's row panel, slab 0
+  int a_voff[G::A_ITEMS];
 #pragma unroll
   for (int i = 0; i < G::A_ITEMS; ++i) {
     const int idx = tid + NT * i;
-    a_off[i] = (idx / CH) * (int)lda + (idx % CH) * 8;
+    a_voff[i] = ((idx / CH) * (int)lda + (idx % CH) * 8) * 4;
   }
 
-  // ---- global -> registers ------------------------------------------------
-  float ra[G::A_ITEMS][8];
-  float rb[G::B_ITEMS][8];
-  auto gload = [&](int k0) {
-    const bool full = interior && k0 + BK <= K;
-    if (full) {
-      const float *Ak = Ab + k0;
+  // ---- global -> registers (two register sets, selected at compile time) --
+  float ra[2][G::A_ITEMS][8];
+  float rb[2][G::B_ITEMS][8];
+  // FAST: every element of the slab lies in [0, K) (or the data is never
+  // consumed).  Otherwise elements outside [0, K) read as zero.
+  auto gload = [&](auto S, auto F, int k0) {
+    constexpr int set = decltype(S)::value;
+    constexpr bool FAST = decltype(F)::value;
+    if (FAST) {
 #pragma unroll
       for (int i = 0; i < G::A_ITEMS; ++i) {
-        const float *p = Ak + a_off[i];
+        const int off = a_voff[i] + k0 * 4;
         if (VEC) {
-          const float4 v0 = *reinterpret_cast<const float4 *>(p);
-          const float4 v1 = *reinterpret_cast<const float4 *>(p + 4);
-          ra[i][0] = v0.x; ra[i][1] = v0.y; ra[i][2] = v0.z; ra[i][3] = v0.w;
-          ra[i][4] = v1.x; ra[i][5] = v1.y; ra[i][6] = v1.z; ra[i][7] = v1.w;
+          // (bit-cast whole vectors: a bit_cast of a vector element is not
+          // element-indexed in this compiler)
+          const float4 v0 =
+              __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrcA, off, 0, 0));
+          const float4 v1 =
+              __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrcA, off + 16, 0, 0));
+          ra[set][i][0] = v0.x; ra[set][i][1] = v0.y; ra[set][i][2] = v0.z; ra[set][i][3] = v0.w;
+          ra[set][i][4] = v1.x; ra[set][i][5] = v1.y; ra[set][i][6] = v1.z; ra[set][i][7] = v1.w;
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) ra[i][e] = p[e];
+          for (int e = 0; e < 8; ++e)
+            ra[set][i][e] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rsrcA, off + 4 * e, 0, 0));
         }
       }
-#pragma unroll
-      for (int i = 0; i < G::B_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int n = idx % BN;
-        const int c = __builtin_amdgcn_readfirstlane(idx / BN);  // wave-uniform
-        const float *Bk = Bb + (int64_t)(k0 + 8 * c) * ldb;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) rb[i][e] = Bk[(int64_t)e * ldb + n];
-      }
-    } else {
+    } else {  // partial slab: per-element offsets, invalid ones pushed out of range
 #pragma unroll
       for (int i = 0; i < G::A_ITEMS; ++i) {
         const int idx = tid + NT * i;
-        const int r = idx / CH, k = k0 + (idx % CH) * 8;
-        const float *p = Ab + (int64_t)r * lda + k;
+        const int k = k0 + (idx % CH) * 8;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ra[i][e] = (r < Mr && k + e < K) ? p[e] : 0.0f;
+        for (int e = 0; e < 8; ++e) {
+          const int off = (k + e >= 0 && k + e < K) ? a_voff[i] + (k0 + e) * 4 : (int)0x80000000;
+          ra[set][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrcA, off, 0, 0));
+        }
       }
+    }
 #pragma unroll
-      for (int i = 0; i < G::B_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int n = idx % BN, k = k0 + (idx / BN) * 8;
-        const float *p = Bb + (int64_t)k * ldb + n;
-        const bool nin = n < Nr;
+    for (int i = 0; i < G::B_ITEMS; ++i) {
+      const int idx = tid + NT * i;
+      const int n = idx % BN;
+      const int c = __builtin_amdgcn_readfirstlane(idx / BN);  // wave-uniform
 #pragma unroll
-        for (int e = 0; e < 8; ++e) rb[i][e] = (nin && k + e < K) ? p[(int64_t)e * ldb] : 0.0f;
+      for (int e = 0; e < 8; ++e) {
+        // one resource per B row: rows at or past K have no valid bytes,
+        // columns at or past N fall beyond the row's valid bytes
+        const int k = k0 + 8 * c + e;
+        // (a clamped full-slab load may still touch slab 0, which can start
+        // before k = 0: those rows are skipped so that no address precedes B)
+        const bool kin = k >= 0 && (FAST || k < K);
+        const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(B + (int64_t)(kin ? k : 0) * ldb + n0), (short)0,
+            kin ? colsB * 4 : 0, kBufferFlags);
+        rb[set][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, n * 4, 0, 0));
       }
     }
   };
@@ -160,7 +186,8 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       if constexpr (NP == 3) l[e] = x2;
     }
   };
-  auto sstore = [&](int stage) {
+  auto sstore = [&](auto S, int stage) {
+    constexpr int set = decltype(S)::value;
     __bf16 *sA = lds + stage * G::STAGE;
     __bf16 *sB = sA + NP * G::PLANE_A;
 #pragma unroll
@@ -168,7 +195,7 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       const int idx = tid + NT * i;
       const int r = idx / CH, c = idx % CH;
       bf16x8 h, m, l;
-      split8(ra[i], h, m, l);
+      split8(ra[set][i], h, m, l);
       const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
       *reinterpret_cast<bf16x8 *>(sA + off) = h;
       *reinterpret_cast<bf16x8 *>(sA + G::PLANE_A + off) = m;
@@ -179,7 +206,7 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       const int idx = tid + NT * i;
       const int n = idx % BN, c = idx / BN;
       bf16x8 h, m, l;
-      split8(rb[i], h, m, l);
+      split8(rb[set][i], h, m, l);
       const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
       *reinterpret_cast<bf16x8 *>(sB + off) = h;
       *reinterpret_cast<bf16x8 *>(sB + G::PLANE_B + off) = m;
@@ -254,18 +281,46 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
   };
 
-  // ---- K loop: loads of slab t+1 in flight during slab t's MFMAs ---------
+  // ---- K loop ---------------------------------------------------------------
+  // Slab t is multiplied from LDS stage t%2 while (a) the global loads of slab
+  // t+2 are in flight into one register set and (b) slab t+1, loaded during
+  // slab t-1 into the other set, is split and written to stage (t+1)%2.  Both
+  // are independent of slab t's MFMAs, so the scheduler interleaves them; one
+  // barrier per slab separates the LDS stages.
+  // The slab grid ends exactly at K (slab s covers [kbase + s*BK, +BK) with
+  // kbase = K - KT*BK <= 0), so only slab 0 can be partial; it is loaded with
+  // masking in the prologue.  Loads past the last slab are clamped to it
+  // (in-bounds reads whose data is never consumed), so both halves of the loop
+  // issue the same instructions on every iteration and each wait covers only
+  // the loads it needs.
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using Fast = std::true_type;
+  using Masked = std::false_type;
   const int KT = (K + BK - 1) / BK;
-  gload(0);
-  sstore(0);
+  const int kbase = K - KT * BK;
+  auto kslab = [&](int sl) { return kbase + (sl < KT ? sl : KT - 1) * BK; };
+  gload(S0{}, Masked{}, kbase);
+  sstore(S0{}, 0);
+  if (KT > 1) gload(S1{}, Fast{}, kslab(1));
+  else gload(S1{}, Masked{}, kbase);
   __syncthreads();
-  for (int t = 0; t < KT; ++t) {
-    const bool more = t + 1 < KT;
-    if (more) gload((t + 1) * BK);
+  int t = 0;
+  for (; t + 2 <= KT; t += 2) {
+    gload(S0{}, Fast{}, kslab(t + 2));
 #pragma unroll
-    for (int ks = 0; ks < G::KS; ++ks) mfma_step(t & 1, ks);
-    if (more) sstore((t + 1) & 1);
+    for (int ks = 0; ks < G::KS; ++ks) mfma_step(0, ks);
+    sstore(S1{}, 1);
     __syncthreads();
+    gload(S1{}, Fast{}, kslab(t + 3));
+#pragma unroll
+    for (int ks = 0; ks < G::KS; ++ks) mfma_step(1, ks);
+    sstore(S0{}, 0);
+    __syncthreads();
+  }
+  if (t < KT) {  // odd slab count: the last slab sits in stage 0
+#pragma unroll
+    for (int ks = 0; ks < G::KS; ++ks) mfma_step(0, ks);
   }
 
   // ---- peeled epilogue ----------------------------------------------------

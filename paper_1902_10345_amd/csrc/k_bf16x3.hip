@@ -24,11 +24,13 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const int tiles_n = (int)((g.N + BN - 1) / BN);
   const int64_t nwg = (int64_t)tiles_m * tiles_n;
   if (nwg > 0x7fffffff) { set_error("gemm_f32_3xbf16: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
-  if ((int64_t)BM * g.lda + g.K >= (int64_t)1 << 31) {
+  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 || g.ldb * 4 >= ((int64_t)1 << 31)) {
     set_error("gemm_f32_3xbf16: lda too large for 32-bit tile offsets");
     return GEMM_STATUS_UNSUPPORTED;
   }
-  const bool vec = g.lda % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
+  // 128-bit loads of A rows need 16-byte aligned slab starts: the slab grid
+  // ends at K, so K must be a multiple of 4 as well as lda.
+  const bool vec = g.lda % 4 == 0 && g.K % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
   const bool beta = g.beta != 0.0f;
   dim3 grid((unsigned)nwg), block(64 * NW);
 #define MM_LAUNCH(V, BT)                                                                    \
@@ -64,13 +66,15 @@ struct Bx3Config {
   int np;
 };
 static const Bx3Config kBx3Configs[] = {
-    {{256, 256, 32, "bx3_256x256x32_8w128x64_p3"}, 2},
+    {{256, 256, 16, "bx3_256x256x16_8w128x64_p3"}, 2},
     {{128, 128, 32, "bx3_128x128x32_4w64x64_p3"}, 2},
     {{256, 128, 32, "bx3_256x128x32_8w64x64_p3"}, 2},
-    {{256, 256, 32, "bx3_256x256x32_4w128x128_p3"}, 2},
+    {{256, 256, 32, "bx3_256x256x32_8w128x64_p3"}, 2},
     {{256, 256, 16, "bx3_256x256x16_8w128x64_p6"}, 3},
     {{128, 128, 32, "bx3_128x128x32_4w64x64_p6"}, 3},
     {{64, 64, 32, "bx3_64x64x32_4w32x32_p3"}, 2},
+    {{256, 256, 16, "bx3_256x256x16_4w128x128_p3"}, 2},
+    {{128, 128, 16, "bx3_128x128x16_4w64x64_p3"}, 2},
 };
 
 int bx3_num_configs() { return (int)(sizeof(kBx3Configs) / sizeof(kBx3Configs[0])); }
@@ -92,13 +96,15 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
 
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
   switch (cfg) {
-    case 0: return bx3::launch<256, 256, 32, 128, 64, 2, 8>(g, s);
+    case 0: return bx3::launch<256, 256, 16, 128, 64, 2, 8>(g, s);
     case 1: return bx3::launch<128, 128, 32, 64, 64, 2, 4>(g, s);
     case 2: return bx3::launch<256, 128, 32, 64, 64, 2, 8>(g, s);
-    case 3: return bx3::launch<256, 256, 32, 128, 128, 2, 4>(g, s);
+    case 3: return bx3::launch<256, 256, 32, 128, 64, 2, 8>(g, s);
     case 4: return bx3::launch<256, 256, 16, 128, 64, 3, 8>(g, s);
     case 5: return bx3::launch<128, 128, 32, 64, 64, 3, 4>(g, s);
     case 6: return bx3::launch<64, 64, 32, 32, 32, 2, 4>(g, s);
+    case 7: return bx3::launch<256, 256, 16, 128, 128, 2, 4>(g, s);
+    case 8: return bx3::launch<128, 128, 16, 64, 64, 2, 4>(g, s);
     default: set_error("gemm_f32_3xbf16: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

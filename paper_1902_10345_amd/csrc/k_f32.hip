@@ -20,6 +20,9 @@
 namespace mm {
 namespace f32 {
 
+// Word 3 of a raw buffer resource (32-bit data format, no swizzle).
+constexpr int kBufferFlags = 0x00020000;
+
 // Guarded load of the four consecutive elements (r, c..c+3) of a row-major
 // matrix with R rows and Cc columns; out-of-range elements read as zero.
 template <bool VEC>
@@ -73,7 +76,38 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(
   const float *Bb = B + n0;
 
   float4 ra[LA], rb[LB];
+  // Interior slabs use raw buffer loads: an SGPR resource per operand (the
+  // B resource is rebased to the slab's first row) and fixed 32-bit lane
+  // offsets, so no 64-bit address arithmetic runs per load.  Edge slabs take
+  // the guarded path.  The launcher guarantees 32-bit byte offsets.
+  const bool interior = Mr >= BM && Nr >= BN;
+  const __amdgpu_buffer_rsrc_t rsrcA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(Ab), (short)0, interior ? (int)(((int64_t)(BM - 1) * lda + K) * 4) : 0,
+      kBufferFlags);
+  int a_voff[LA], b_voff[LB];
+#pragma unroll
+  for (int i = 0; i < LA; ++i) {
+    const int idx = tid + NT * i;
+    a_voff[i] = ((idx / (BK / 4)) * (int)lda + (idx % (BK / 4)) * 4) * 4;
+  }
+#pragma unroll
+  for (int i = 0; i < LB; ++i) {
+    const int idx = tid + NT * i;
+    b_voff[i] = ((idx / (BN / 4)) * (int)ldb + (idx % (BN / 4)) * 4) * 4;
+  }
   auto gload = [&](int k0) {
+    if (VEC && interior && k0 + BK <= K) {
+      const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(Bb + (int64_t)k0 * ldb), (short)0,
+          (int)(((int64_t)(BK - 1) * ldb + BN) * 4), kBufferFlags);
+#pragma unroll
+      for (int i = 0; i < LA; ++i)
+        ra[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrcA, a_voff[i] + k0 * 4, 0, 0));
+#pragma unroll
+      for (int i = 0; i < LB; ++i)
+        rb[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrcB, b_voff[i], 0, 0));
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int idx = tid + NT * i;
@@ -188,6 +222,11 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const int tiles_n = (int)((g.N + BN - 1) / BN);
   const int64_t nwg = (int64_t)tiles_m * tiles_n;
   if (nwg > 0x7fffffff) { set_error("gemm_f32: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
+  if (((int64_t)BM * g.lda + g.K) * 4 >= ((int64_t)1 << 31) ||
+      ((int64_t)BK * g.ldb + BN) * 4 >= ((int64_t)1 << 31)) {
+    set_error("gemm_f32: leading dimension too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
   const bool vec = g.lda % 4 == 0 && g.ldb % 4 == 0 && g.ldc % 4 == 0 &&
                    ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0 &&
                    ((uintptr_t)g.C & 15) == 0;

@@ -10,6 +10,7 @@
 // qbT is B's code matrix transposed (column j contiguous), so both operands are
 // k-contiguous and stage into LDS without a transpose.  Codes in [K, Kp) are 0.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -18,6 +19,9 @@ namespace mm {
 namespace fp8 {
 
 constexpr int KP_ALIGN = 128;
+// Word 3 of a raw buffer resource (32-bit data format, no swizzle).
+constexpr int kBufferFlags = 0x00020000;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct Layout {
   int64_t Kp;
@@ -101,24 +105,92 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(int M, int K, int64_t K
   }
 }
 
+// Single-pass variant for rows of at most 256*4*CH elements: the row stays
+// in registers between the amax reduction and the encoding (one HBM read).
+// Lane t owns elements 4t + 1024j .. +3 (j < CH) and stores their 4 codes as
+// one 32-bit word.  VEC: lda % 4 == 0 and A 16-byte aligned.
+template <int CH, bool VEC>
+__global__ __launch_bounds__(256) void quant_rows_reg_kernel(int M, int K, int64_t Kp,
+                                                             const float *__restrict__ A,
+                                                             int64_t lda, uint8_t *__restrict__ qa,
+                                                             float *__restrict__ sa) {
+  __shared__ float red[4];
+  const int i = blockIdx.x;
+  const float *row = A + (int64_t)i * lda;
+  float v[CH][4];
+  float m = 0.0f;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const int k = 4 * (int)threadIdx.x + 1024 * j;
+    if (VEC && k + 3 < K) {
+      const float4 x = *reinterpret_cast<const float4 *>(row + k);
+      v[j][0] = x.x; v[j][1] = x.y; v[j][2] = x.z; v[j][3] = x.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[j][e] = k + e < K ? row[k + e] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m = fmaxf(m, fabsf(v[j][e]));
+  }
+  m = warp_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float s = (m == 0.0f) ? 1.0f : m / 448.0f;
+  if (threadIdx.x == 0) sa[i] = s;
+  uint8_t *q = qa + (int64_t)i * Kp;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const int k = 4 * (int)threadIdx.x + 1024 * j;
+    if (k >= Kp) continue;
+    uint32_t word = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) word |= (k + e < K ? e4m3_encode(v[j][e] / s) : 0u) << (8 * e);
+    *reinterpret_cast<uint32_t *>(q + k) = word;
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     p[i] = 0u;
 }
 
-// Column amax of B over a K range: grid (ceil(N/256), ksplit).  Non-negative
-// binary32 values order like their bit patterns, so atomicMax on the bits is
-// an exact, order-independent maximum.
-__global__ __launch_bounds__(256) void col_amax_kernel(int K, int N, const float *__restrict__ B,
-                                                       int64_t ldb, int krange,
-                                                       uint32_t *__restrict__ amax_bits) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  const int k0 = blockIdx.y * krange;
-  const int k1 = min(K, k0 + krange);
-  float m = 0.0f;
-  for (int k = k0; k < k1; ++k) m = fmaxf(m, fabsf(B[(int64_t)k * ldb + j]));
-  atomicMax(amax_bits + j, __builtin_bit_cast(uint32_t, m));
+// Column amax over a 256-row x 64-column block: 16 lanes x float4 span the
+// 64 columns, 16 lane-rows step through the 256 rows; an LDS reduction over
+// the lane-rows, then one atomicMax per column.  VEC: ldb % 4 == 0, B aligned.
+template <bool VEC>
+__global__ __launch_bounds__(256) void col_amax4_kernel(int K, int N, const float *__restrict__ B,
+                                                        int64_t ldb,
+                                                        uint32_t *__restrict__ amax_bits) {
+  __shared__ float red[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int j0 = blockIdx.x * 64 + tx * 4;
+  const int k0 = blockIdx.y * 256;
+  float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int r = ty; r < 256; r += 16) {
+    const int k = k0 + r;
+    if (k >= K) break;
+    const float *p = B + (int64_t)k * ldb + j0;
+    if (VEC && j0 + 3 < N) {
+      const float4 x = *reinterpret_cast<const float4 *>(p);
+      m[0] = fmaxf(m[0], fabsf(x.x)); m[1] = fmaxf(m[1], fabsf(x.y));
+      m[2] = fmaxf(m[2], fabsf(x.z)); m[3] = fmaxf(m[3], fabsf(x.w));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (j0 + e < N) m[e] = fmaxf(m[e], fabsf(p[e]));
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[ty][tx * 4 + e] = m[e];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    float x = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x = fmaxf(x, red[r][threadIdx.x]);
+    const int j = blockIdx.x * 64 + (int)threadIdx.x;
+    if (j < N) atomicMax(amax_bits + j, __builtin_bit_cast(uint32_t, x));
+  }
 }
 
 // Quantise a 64(k) x 64(n) block of B with the column scales and store it
@@ -188,37 +260,49 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(
   const int m0 = tm * BM, n0 = tn * BN;
   const int Mr = M - m0, Nr = N - n0;
 
-  uint4 ra[G::A_CH], rb[G::B_CH];
-  auto gload = [&](int64_t k0) {
+  // Raw buffer loads: rows past M (N) lie beyond num_records and read as 0;
+  // lane offsets are 32-bit (the launcher bounds 256 * Kp < 2^31).
+  const int rowsA = Mr < BM ? Mr : BM, rowsB = Nr < BN ? Nr : BN;
+  const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(qa + (int64_t)m0 * Kp), (short)0, (int)(rowsA * Kp), kBufferFlags);
+  const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(qbT + (int64_t)n0 * Kp), (short)0, (int)(rowsB * Kp), kBufferFlags);
+  int voA[G::A_CH], voB[G::B_CH];
 #pragma unroll
-    for (int i = 0; i < G::A_CH; ++i) {
-      const int idx = tid + G::NT * i;
-      const int r = idx >> 3, c = idx & 7;
-      ra[i] = r < Mr ? *reinterpret_cast<const uint4 *>(qa + (int64_t)(m0 + r) * Kp + k0 + c * 16)
-                     : make_uint4(0, 0, 0, 0);
-    }
+  for (int i = 0; i < G::A_CH; ++i) {
+    const int idx = tid + G::NT * i;
+    voA[i] = (idx >> 3) * (int)Kp + (idx & 7) * 16;
+  }
 #pragma unroll
-    for (int i = 0; i < G::B_CH; ++i) {
-      const int idx = tid + G::NT * i;
-      const int r = idx >> 3, c = idx & 7;
-      rb[i] = r < Nr ? *reinterpret_cast<const uint4 *>(qbT + (int64_t)(n0 + r) * Kp + k0 + c * 16)
-                     : make_uint4(0, 0, 0, 0);
-    }
+  for (int i = 0; i < G::B_CH; ++i) {
+    const int idx = tid + G::NT * i;
+    voB[i] = (idx >> 3) * (int)Kp + (idx & 7) * 16;
+  }
+  u32x4 ra[2][G::A_CH], rb[2][G::B_CH];
+  auto gload = [&](auto S, int k0) {
+    constexpr int set = decltype(S)::value;
+#pragma unroll
+    for (int i = 0; i < G::A_CH; ++i)
+      ra[set][i] = __builtin_amdgcn_raw_buffer_load_b128(rsA, voA[i] + k0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < G::B_CH; ++i)
+      rb[set][i] = __builtin_amdgcn_raw_buffer_load_b128(rsB, voB[i] + k0, 0, 0);
   };
-  auto sstore = [&](int stage) {
+  auto sstore = [&](auto S, int stage) {
+    constexpr int set = decltype(S)::value;
     uint8_t *sA = lds + stage * G::STAGE;
     uint8_t *sB = sA + BM * G::BK;
 #pragma unroll
     for (int i = 0; i < G::A_CH; ++i) {
       const int idx = tid + G::NT * i;
       const int r = idx >> 3, c = idx & 7;
-      *reinterpret_cast<uint4 *>(sA + r * G::BK + ((c ^ swz8(r)) << 4)) = ra[i];
+      *reinterpret_cast<u32x4 *>(sA + r * G::BK + ((c ^ swz8(r)) << 4)) = ra[set][i];
     }
 #pragma unroll
     for (int i = 0; i < G::B_CH; ++i) {
       const int idx = tid + G::NT * i;
       const int r = idx >> 3, c = idx & 7;
-      *reinterpret_cast<uint4 *>(sB + r * G::BK + ((c ^ swz8(r)) << 4)) = rb[i];
+      *reinterpret_cast<u32x4 *>(sB + r * G::BK + ((c ^ swz8(r)) << 4)) = rb[set][i];
     }
   };
 
@@ -261,17 +345,35 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(
                                                                      0, 0, 0, 0);
   };
 
+  // K loop: slab t multiplied from stage t%2 while slab t+2 is in flight into
+  // one register set and slab t+1 (already in the other set) is written to
+  // the other stage; one barrier per slab.  Loads past the last slab are
+  // clamped to it (in-bounds reads never consumed) so that every iteration
+  // issues the same instructions and each wait covers only what it needs.
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
   const int KT = (int)(Kp / G::BK);
-  gload(0);
-  sstore(0);
+  auto kslab = [&](int sl) { return (sl < KT ? sl : KT - 1) * G::BK; };
+  gload(S0{}, 0);
+  sstore(S0{}, 0);
+  gload(S1{}, kslab(1));
   __syncthreads();
-  for (int t = 0; t < KT; ++t) {
-    const bool more = t + 1 < KT;
-    if (more) gload((int64_t)(t + 1) * G::BK);
-    mfma_step(t & 1, 0);
-    mfma_step(t & 1, 1);
-    if (more) sstore((t + 1) & 1);
+  int t = 0;
+  for (; t + 2 <= KT; t += 2) {
+    gload(S0{}, kslab(t + 2));
+    mfma_step(0, 0);
+    mfma_step(0, 1);
+    sstore(S1{}, 1);
     __syncthreads();
+    gload(S1{}, kslab(t + 3));
+    mfma_step(1, 0);
+    mfma_step(1, 1);
+    sstore(S0{}, 0);
+    __syncthreads();
+  }
+  if (t < KT) {
+    mfma_step(0, 0);
+    mfma_step(0, 1);
   }
 
 #pragma unroll
@@ -315,19 +417,44 @@ gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, in
   float *sb = reinterpret_cast<float *>(base + L.sb);
   uint32_t *amax = reinterpret_cast<uint32_t *>(base + L.amax);
   if (M > 0) {
-    hipLaunchKernelGGL(fp8::quant_rows_kernel, dim3((unsigned)M), dim3(256), 0, s, (int)M, (int)K,
-                       L.Kp, A, lda, qa, sa);
+    const bool vec = lda % 4 == 0 && ((uintptr_t)A & 15) == 0;
+    const int ch = (int)((L.Kp + 1023) / 1024);
+#define MM_QROWS(CH)                                                                             \
+  do {                                                                                           \
+    if (vec)                                                                                     \
+      hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, true>), dim3((unsigned)M), dim3(256), 0, \
+                         s, (int)M, (int)K, L.Kp, A, lda, qa, sa);                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, false>), dim3((unsigned)M), dim3(256),  \
+                         0, s, (int)M, (int)K, L.Kp, A, lda, qa, sa);                            \
+  } while (0)
+    switch (ch) {
+      case 1: MM_QROWS(1); break;
+      case 2: MM_QROWS(2); break;
+      case 3: MM_QROWS(3); break;
+      case 4: MM_QROWS(4); break;
+      case 5: MM_QROWS(5); break;
+      case 6: MM_QROWS(6); break;
+      case 7: MM_QROWS(7); break;
+      case 8: MM_QROWS(8); break;
+      default:
+        hipLaunchKernelGGL(fp8::quant_rows_kernel, dim3((unsigned)M), dim3(256), 0, s, (int)M,
+                           (int)K, L.Kp, A, lda, qa, sa);
+    }
+#undef MM_QROWS
     if (gemm_status st = check_launch("quant_rows_kernel")) return st;
   }
   if (N > 0) {
     const unsigned fg = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
     hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, N);
     if (gemm_status st = check_launch("fill_u32_kernel")) return st;
-    const int krange = 128;
-    const unsigned ksplit = (unsigned)std::max<int64_t>(1, (K + krange - 1) / krange);
-    hipLaunchKernelGGL(fp8::col_amax_kernel, dim3((unsigned)((N + 255) / 256), ksplit), dim3(256),
-                       0, s, (int)K, (int)N, B, ldb, krange, amax);
-    if (gemm_status st = check_launch("col_amax_kernel")) return st;
+    const bool vec = ldb % 4 == 0 && ((uintptr_t)B & 15) == 0;
+    const dim3 ag((unsigned)((N + 63) / 64), (unsigned)std::max<int64_t>(1, (K + 255) / 256));
+    if (vec)
+      hipLaunchKernelGGL(fp8::col_amax4_kernel<true>, ag, dim3(256), 0, s, (int)K, (int)N, B, ldb, amax);
+    else
+      hipLaunchKernelGGL(fp8::col_amax4_kernel<false>, ag, dim3(256), 0, s, (int)K, (int)N, B, ldb, amax);
+    if (gemm_status st = check_launch("col_amax4_kernel")) return st;
     hipLaunchKernelGGL(fp8::quant_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)((N + 63) / 64)),
                        dim3(256), 0, s, (int)K, (int)N, L.Kp, B, ldb, amax, qb, sb);
     if (gemm_status st = check_launch("quant_cols_t_kernel")) return st;
@@ -340,6 +467,10 @@ gemm_status fp8_gemm_run(int64_t M, int64_t N, int64_t K, float alpha, const voi
   const fp8::Layout L = fp8::layout(M, N, K);
   const uint8_t *base = static_cast<const uint8_t *>(ws);
   constexpr int BM = 256, BN = 256;
+  if ((int64_t)BM * L.Kp >= ((int64_t)1 << 31)) {
+    set_error("gemm_fp8: K too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
   const int tiles_m = (int)((M + BM - 1) / BM), tiles_n = (int)((N + BN - 1) / BN);
   const dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
   const uint8_t *qa = base + L.qa, *qb = base + L.qb;

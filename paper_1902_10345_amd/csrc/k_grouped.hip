@@ -111,23 +111,31 @@ gemm_status grouped_build(const gemm_problem *probs, int count, const int *varia
   descs.resize(count);
   starts.resize((size_t)count + 1);
   const double small_cost = tuned_small_cost();
+  // Longest tiles first: a tile's time grows with K, so handing out the
+  // deepest problems' tiles first keeps the end of the queue short.  The
+  // table order changes only the schedule, never a problem's result.
+  std::vector<int> order(count);
+  for (int p = 0; p < count; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return probs[a].K > probs[b].K; });
   int64_t t = 0;
-  for (int p = 0; p < count; ++p) {
+  for (int slot = 0; slot < count; ++slot) {
+    const int p = order[slot];
     const gemm_problem &q = probs[p];
-    Desc &d = descs[p];
+    Desc &d = descs[slot];
     d.A = q.A; d.B = q.B; d.C = q.C;
     d.lda = q.lda; d.ldb = q.ldb; d.ldc = q.ldc;
     d.M = (int)q.M; d.N = (int)q.N; d.K = (int)q.K;
     d.alpha = q.alpha; d.beta = q.beta;
     d.variant = variant ? variant[p] : grouped_pick_variant(q.M, q.N, small_cost);
     const int bm = grp::kBM[d.variant], bn = grp::kBN[d.variant];
-    d.vec = (q.lda % 4 == 0 && ((uintptr_t)q.A & 15) == 0) ? 1 : 0;
+    d.vec = (q.lda % 4 == 0 && q.K % 4 == 0 && ((uintptr_t)q.A & 15) == 0) ? 1 : 0;
     // problems that need no MFMA work contribute no tiles; the host handles
     // them (no-op or C <- beta*C) before the launch
     const bool work = q.M > 0 && q.N > 0 && q.K > 0 && q.alpha != 0.0f;
     d.tiles_n = work ? (int)((q.N + bn - 1) / bn) : 0;
     const int64_t tiles = work ? ((q.M + bm - 1) / bm) * (int64_t)d.tiles_n : 0;
-    starts[p] = (int)t;
+    starts[slot] = (int)t;
     t += tiles;
     if (t > 0x7fffffff) { set_error("grouped_gemm: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
   }
