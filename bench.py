@@ -218,18 +218,38 @@ def run_serving(torch, mm, seconds, rate=2000.0):
 
 
 def run_profile(torch, mm):
-    """Headline launches and a 1 GiB copy, for rocprofv3 counter runs."""
+    """Launches of every timed kernel and a 1 GiB copy (the calibration of the
+    byte counters), for rocprofv3 counter runs."""
     M = N = K = 4096
     _, (A, B, C) = _dev_inputs(M, N, K, 2, torch)
     for i in range(5):
         mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, C, N, 3)
         mm.gemm_f32(M, N, K, 1.5, A, K, B, N, 0.5, C, N)
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    An, Bn = torch.randn(M, K, device="cuda"), torch.randn(K, N, device="cuda")
+    mm.fp8_quantize(M, N, K, An, K, Bn, N, ws, nbytes)
+    for i in range(5):
+        mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, C, N)
+    del An, Bn, ws
+    import seeded_inputs as si
+    dev = []
+    for (Mg, Ng, Kg, Ag, Bg) in si.grouped_problems(512, seed=5):
+        dC = torch.empty((Mg, Ng), dtype=torch.float32, device="cuda")
+        dev.append((Mg, Ng, Kg, torch.from_numpy(Ag).cuda(), Kg, torch.from_numpy(Bg).cuda(), Ng,
+                    dC, Ng, 1.0, 0.0))
+    arr = mm.problem_array(dev)
+    gws_bytes = mm.grouped_gemm_workspace_bytes(len(dev))
+    gws = torch.empty(gws_bytes, dtype=torch.uint8, device="cuda")
+    for i in range(5):
+        mm.grouped_gemm(arr, len(dev), mm.PATH_3XBF16, None, gws, gws_bytes)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    _log("profile run done: 5 x gemm_bx3, 5 x gemm_f32 (4096^3), 5 x copy of 1 GiB")
+    _log("profile run done: 5 x gemm_bx3, gemm_f32, gemm_fp8 (4096^3), 5 x grouped 512, "
+         "5 x copy of 1 GiB")
 
 
 def main():
@@ -324,6 +344,17 @@ def main():
         _, (A4, B4, C4) = _dev_inputs(M4, M4, M4, 1, torch)
         one("f32_valu_256^3", lambda: mm.gemm_f32(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4),
             2.0 * M4 ** 3, PEAK_FP32_VALU, "fp32_valu_peak")
+        one("3xbf16_n3_256^3",
+            lambda: mm.gemm_f32_3xbf16(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4, 3),
+            2.0 * M4 ** 3, PEAK_BF16_MFMA, "bf16_peak")
+        del A4, B4, C4
+        # one GPU's share of the 4096^3 product under eight-way row sharding
+        M5 = 512
+        _, (A5, B5, C5) = _dev_inputs(M5, N, K, 8, torch)
+        one("3xbf16_n3_512x4096x4096_row_shard",
+            lambda: mm.gemm_f32_3xbf16(M5, N, K, 1.5, A5, K, B5, N, 0.5, C5, N, 3),
+            2.0 * M5 * N * K, PEAK_BF16_MFMA, "bf16_peak")
+        del A5, B5, C5
 
     grouped = None
     if not args.no_grouped:

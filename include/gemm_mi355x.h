@@ -134,15 +134,20 @@ gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream
  * Tile configurations (for the autotuner and for per-configuration tests).
  * Every configuration of a path computes the same operation; results may
  * differ between configurations only by binary32 summation order.
- * path: GEMM_PATH_F32, GEMM_PATH_3XBF16 or GEMM_PATH_FP8.
+ * path: GEMM_PATH_F32, GEMM_PATH_3XBF16, GEMM_PATH_FP8 (quantise A and B into
+ * the workspace, then multiply) or GEMM_PATH_FP8_PREQUANTIZED (multiply the
+ * codes and scales already in the workspace, as gemm_fp8_prequantized; A, B,
+ * lda and ldb are ignored and may be NULL / 0).  The two FP8 paths share one
+ * set of configurations and one autotuner entry per size bucket.
  * gemm_run_config: arguments 1 path, 2 cfg (0 <= cfg < gemm_num_configs, or
  * -1 for the library's default choice), then 3..13 as gemm_f32's 1..11,
  * 14 n_products (3XBF16 only; ignored otherwise), 15 workspace, 16 ws_bytes
- * (FP8 only; ignored otherwise), 17 stream.
+ * (FP8 paths only; ignored otherwise), 17 stream.
  * ---------------------------------------------------------------------- */
 #define GEMM_PATH_F32     0
 #define GEMM_PATH_3XBF16  1
 #define GEMM_PATH_FP8     2
+#define GEMM_PATH_FP8_PREQUANTIZED 3
 int gemm_num_configs(int path);
 const char *gemm_config_name(int path, int cfg);
 /* Default configuration the library picks for this shape on the current device. */

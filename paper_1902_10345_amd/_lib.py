@@ -200,7 +200,7 @@ def fp8_workspace_layout(M, N, K):
     return {"Kp": Kp, "qa": qa, "qb": qb, "sa": sa, "sb": sb}
 
 
-PATH_F32, PATH_3XBF16, PATH_FP8 = 0, 1, 2
+PATH_F32, PATH_3XBF16, PATH_FP8, PATH_FP8_PREQUANTIZED = 0, 1, 2, 3
 
 
 def problem_array(problems):

@@ -40,11 +40,20 @@ COMMON_FLAGS = [
 ]
 
 
+# Per-file additions.  The grouped kernel issues its next-tile dequeue early
+# and reads the result only after the current tile; the atomic optimizer's
+# wave-level rewrite would read (and wait for) it immediately.
+FILE_FLAGS = {
+    "k_grouped.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + COMMON_FLAGS + ["-c", src, "-o", obj]
+    flags = COMMON_FLAGS + FILE_FLAGS.get(os.path.basename(src), [])
+    cmd = [hipcc()] + flags + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [hipcc(), "-x", "hip"] + COMMON_FLAGS + ["-c", src, "-o", obj]
+        cmd = [hipcc(), "-x", "hip"] + flags + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

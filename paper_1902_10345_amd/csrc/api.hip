@@ -78,12 +78,13 @@ static gemm_status check_gemm_args(const char *fn, int64_t M, int64_t N, int64_t
 }
 
 static int pick_config(int path, int n_products, int64_t M, int64_t N, int64_t K) {
+  if (path == GEMM_PATH_FP8_PREQUANTIZED) path = GEMM_PATH_FP8;
   const int t = tuned_config(path, n_products, M, N, K);
   if (t >= 0) return t;
   switch (path) {
     case GEMM_PATH_F32: return f32_default_config(M, N, K);
     case GEMM_PATH_3XBF16: return bx3_default_config(M, N, K, n_products);
-    default: return 0;
+    default: return fp8_default_config(M, N, K);
   }
 }
 
@@ -160,7 +161,8 @@ gemm_status gemm_fp8_scaled(int64_t M, int64_t N, int64_t K, float alpha, const 
   if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
   if ((st = fp8_check_ws(fn, 12, M, N, K, workspace, ws_bytes))) return st;
   if ((st = fp8_quantize_run(M, N, K, A, lda, B, ldb, workspace, stream))) return st;
-  return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
+  return fp8_gemm_run_cfg(M, N, K, alpha, workspace, beta, C, ldc,
+                          pick_config(GEMM_PATH_FP8, 3, M, N, K), stream);
 }
 
 gemm_status fp8_quantize(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
@@ -196,7 +198,8 @@ gemm_status gemm_fp8_prequantized(int64_t M, int64_t N, int64_t K, float alpha,
   if (M == 0 || N == 0) return GEMM_STATUS_OK;
   if (!C) return bad_arg(8, fn, "(C) is NULL");
   if (alpha == 0.0f || K == 0) return scale_c(M, N, beta, C, ldc, stream);
-  return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
+  return fp8_gemm_run_cfg(M, N, K, alpha, workspace, beta, C, ldc,
+                          pick_config(GEMM_PATH_FP8, 3, M, N, K), stream);
 }
 
 gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream_t stream) {
@@ -213,7 +216,8 @@ int gemm_num_configs(int path) {
   switch (path) {
     case GEMM_PATH_F32: return f32_num_configs();
     case GEMM_PATH_3XBF16: return bx3_num_configs();
-    case GEMM_PATH_FP8: return 1;
+    case GEMM_PATH_FP8:
+    case GEMM_PATH_FP8_PREQUANTIZED: return fp8_num_configs();
     default: return 0;
   }
 }
@@ -223,13 +227,14 @@ const char *gemm_config_name(int path, int cfg) {
   switch (path) {
     case GEMM_PATH_F32: return f32_config(cfg).name;
     case GEMM_PATH_3XBF16: return bx3_config(cfg).name;
-    case GEMM_PATH_FP8: return "fp8_256x256x128_w128x128";
+    case GEMM_PATH_FP8:
+    case GEMM_PATH_FP8_PREQUANTIZED: return fp8_config_name(cfg);
     default: return "";
   }
 }
 
 int gemm_default_config(int path, int64_t M, int64_t N, int64_t K) {
-  if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8) return -1;
+  if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8_PREQUANTIZED) return -1;
   return pick_config(path, 3, M, N, K);
 }
 
@@ -241,6 +246,21 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
   const char *fn = "gemm_run_config";
   if (gemm_num_configs(path) == 0) return bad_arg(1, fn, "(path) unknown or not built");
   if (cfg < -1 || cfg >= gemm_num_configs(path)) return bad_arg(2, fn, "(cfg) out of range");
+  if (path == GEMM_PATH_FP8_PREQUANTIZED) {  // operands are the workspace's codes
+    if (M < 0) return bad_arg(3, fn, "(M) must be >= 0");
+    if (N < 0) return bad_arg(4, fn, "(N) must be >= 0");
+    if (K < 0) return bad_arg(5, fn, "(K) must be >= 0");
+    if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL)
+      return bad_arg(3, fn, "size exceeds 2^31-1");
+    gemm_status st = fp8_check_ws(fn, 15, M, N, K, workspace, ws_bytes);
+    if (st) return st;
+    if (ldc < (N > 1 ? N : 1)) return bad_arg(13, fn, "(ldc) must be >= max(1,N)");
+    if (M == 0 || N == 0) return GEMM_STATUS_OK;
+    if (!C) return bad_arg(12, fn, "(C) is NULL");
+    if (alpha == 0.0f || K == 0) return scale_c(M, N, beta, C, ldc, stream);
+    if (cfg < 0) cfg = pick_config(GEMM_PATH_FP8, 3, M, N, K);
+    return fp8_gemm_run_cfg(M, N, K, alpha, workspace, beta, C, ldc, cfg, stream);
+  }
   Checked ck;
   gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
   if (st < 0) {  // argument index shifted by (path, cfg)
@@ -257,7 +277,8 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
   if (path == GEMM_PATH_FP8) {
     if ((st = fp8_check_ws(fn, 15, M, N, K, workspace, ws_bytes))) return st;
     if ((st = fp8_quantize_run(M, N, K, A, lda, B, ldb, workspace, stream))) return st;
-    return fp8_gemm_run(M, N, K, alpha, workspace, beta, C, ldc, stream);
+    if (cfg < 0) cfg = pick_config(GEMM_PATH_FP8, 3, M, N, K);
+    return fp8_gemm_run_cfg(M, N, K, alpha, workspace, beta, C, ldc, cfg, stream);
   }
   GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
   if (cfg < 0) cfg = pick_config(path, n_products, M, N, K);

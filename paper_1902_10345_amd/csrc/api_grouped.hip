@@ -22,7 +22,8 @@ static gemm_status check_problems(const char *fn, const gemm_problem *probs, int
     else if (q.ldc < (q.N > 1 ? q.N : 1)) why = "ldc < max(1,N)";
     else if (q.M > 0 && q.N > 0 && !q.C) why = "C is NULL";
     else if (q.M > 0 && q.N > 0 && q.K > 0 && q.alpha != 0.0f && (!q.A || !q.B)) why = "A or B is NULL";
-    else if ((128 * q.lda + q.K) * 4 >= ((int64_t)1 << 31)) why = "lda too large for 32-bit tile offsets";
+    else if ((128 * q.lda + q.K) * 4 >= ((int64_t)1 << 31) || (32 * q.ldb + q.N) * 4 >= ((int64_t)1 << 31))
+      why = "leading dimension too large for 32-bit tile offsets";
     else if (variant && (variant[p] < 0 || variant[p] >= grouped_num_variants())) {
       set_error(std::string(fn) + ": tile_variant[" + std::to_string(p) + "] out of range");
       return -4;

@@ -112,6 +112,18 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
     const int idx = tid + NT * i;
     a_voff[i] = ((idx / CH) * (int)lda + (idx % CH) * 8) * 4;
   }
+  // byte offsets of this lane's 8 B elements per item inside a full slab
+  // (relative to the slab's first row); columns past N get an offset beyond
+  // any slab resource, so they read as zero
+  int b_voff[G::B_ITEMS][8];
+#pragma unroll
+  for (int i = 0; i < G::B_ITEMS; ++i) {
+    const int idx = tid + NT * i;
+    const int n = idx % BN, c = idx / BN;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      b_voff[i][e] = n < colsB ? ((8 * c + e) * (int)ldb + n) * 4 : (int)0x80000000;
+  }
 
   // ---- global -> registers (two register sets, selected at compile time) --
   float ra[2][G::A_ITEMS][8];
@@ -153,23 +165,34 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
         }
       }
     }
+    if (FAST) {
+      // one resource for the whole slab; per-lane offsets select the rows
+      const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(B + (int64_t)(k0 > 0 ? k0 : 0) * ldb + n0), (short)0,
+          k0 >= 0 ? (int)(((int64_t)(BK - 1) * ldb + colsB) * 4) : 0, kBufferFlags);
 #pragma unroll
-    for (int i = 0; i < G::B_ITEMS; ++i) {
-      const int idx = tid + NT * i;
-      const int n = idx % BN;
-      const int c = __builtin_amdgcn_readfirstlane(idx / BN);  // wave-uniform
+      for (int i = 0; i < G::B_ITEMS; ++i)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        // one resource per B row: rows at or past K have no valid bytes,
-        // columns at or past N fall beyond the row's valid bytes
-        const int k = k0 + 8 * c + e;
-        // (a clamped full-slab load may still touch slab 0, which can start
-        // before k = 0: those rows are skipped so that no address precedes B)
-        const bool kin = k >= 0 && (FAST || k < K);
-        const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float *>(B + (int64_t)(kin ? k : 0) * ldb + n0), (short)0,
-            kin ? colsB * 4 : 0, kBufferFlags);
-        rb[set][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, n * 4, 0, 0));
+        for (int e = 0; e < 8; ++e)
+          rb[set][i][e] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, b_voff[i][e], 0, 0));
+    } else {
+#pragma unroll
+      for (int i = 0; i < G::B_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int n = idx % BN;
+        const int c = __builtin_amdgcn_readfirstlane(idx / BN);  // wave-uniform
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          // one resource per B row: rows outside [0, K) have no valid bytes,
+          // columns at or past N fall beyond the row's valid bytes
+          const int k = k0 + 8 * c + e;
+          const bool kin = k >= 0 && k < K;
+          const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
+              const_cast<float *>(B + (int64_t)(kin ? k : 0) * ldb + n0), (short)0,
+              kin ? colsB * 4 : 0, kBufferFlags);
+          rb[set][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, n * 4, 0, 0));
+        }
       }
     }
   };
@@ -308,11 +331,13 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   int t = 0;
   for (; t + 2 <= KT; t += 2) {
     gload(S0{}, Fast{}, kslab(t + 2));
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < G::KS; ++ks) mfma_step(0, ks);
     sstore(S1{}, 1);
     __syncthreads();
     gload(S1{}, Fast{}, kslab(t + 3));
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < G::KS; ++ks) mfma_step(1, ks);
     sstore(S0{}, 0);

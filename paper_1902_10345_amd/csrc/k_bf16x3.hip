@@ -24,7 +24,8 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const int tiles_n = (int)((g.N + BN - 1) / BN);
   const int64_t nwg = (int64_t)tiles_m * tiles_n;
   if (nwg > 0x7fffffff) { set_error("gemm_f32_3xbf16: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
-  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 || g.ldb * 4 >= ((int64_t)1 << 31)) {
+  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 ||
+      ((int64_t)BK * g.ldb + g.N) * 4 >= ((int64_t)1 << 31)) {
     set_error("gemm_f32_3xbf16: lda too large for 32-bit tile offsets");
     return GEMM_STATUS_UNSUPPORTED;
   }

@@ -45,7 +45,7 @@ __device__ __forceinline__ float4 load4(const float *__restrict__ base, int64_t 
 
 // BM x BN tile, BK-deep slabs, RM x RN micro-tile per lane, 256 lanes.
 // Lane (tx, ty): rows ty + TY*r (r < RM), columns h*(BN/NH) + tx*4 + c.
-template <int BM, int BN, int BK, int RM, int RN, bool VEC, bool BETA>
+template <int BM, int BN, int BK, int RM, int RN, int U, bool VEC, bool BETA>
 __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(
     int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda,
     const float *__restrict__ B, int64_t ldb, float beta, float *__restrict__ C,
@@ -145,9 +145,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(
   auto compute = [&](int s) {
     const float *As = lds + s * (A_ST + B_ST);
     const float *Bs = As + A_ST;
-    // Not unrolled: a full unroll lets the scheduler hoist every slab read
-    // and spill; one 4-deep step already issues RM*RN*4 independent FMAs.
-#pragma unroll 1
+    // Unrolled U times (1 or 2): a full unroll lets the scheduler hoist every
+    // slab read and spill; two steps let the next step's LDS reads overlap
+    // the current step's FMAs.  One 4-deep step issues RM*RN*4 independent FMAs.
+#pragma unroll U
     for (int kk = 0; kk < BK; kk += 4) {
       float4 a[RM];
       float4 b[4][NH];
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(
   }
 }
 
-template <int BM, int BN, int BK, int RM, int RN>
+template <int BM, int BN, int BK, int RM, int RN, int U>
 gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const int tiles_m = (int)((g.M + BM - 1) / BM);
   const int tiles_n = (int)((g.N + BN - 1) / BN);
@@ -233,7 +234,7 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const bool beta = g.beta != 0.0f;
   dim3 grid((unsigned)nwg), block(256);
 #define MM_LAUNCH(V, BT)                                                                     \
-  hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, BK, RM, RN, V, BT>), grid, block, 0, s,        \
+  hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, BK, RM, RN, U, V, BT>), grid, block, 0, s,     \
                      (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, \
                      g.C, g.ldc, tiles_m, tiles_n)
   if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
@@ -249,6 +250,8 @@ static const TileConfig kF32Configs[] = {
     {128, 128, 32, "f32_128x128x32_r8x8"},
     {64, 64, 32, "f32_64x64x32_r4x4"},
     {128, 64, 32, "f32_128x64x32_r8x4"},
+    {128, 128, 32, "f32_128x128x32_r8x8_u2"},
+    {128, 64, 32, "f32_128x64x32_r8x4_u2"},
 };
 
 int f32_num_configs() { return (int)(sizeof(kF32Configs) / sizeof(kF32Configs[0])); }
@@ -257,7 +260,7 @@ const TileConfig &f32_config(int i) { return kF32Configs[i]; }
 int f32_default_config(int64_t M, int64_t N, int64_t K) {
   (void)K;
   const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-  if (big >= 2 * (int64_t)num_cus()) return 0;
+  if (big >= 2 * (int64_t)num_cus()) return 3;  // 128 x 128, k loop unrolled by 2
   const int64_t mid = ((M + 127) / 128) * ((N + 63) / 64);
   if (mid >= (int64_t)num_cus()) return 2;
   return 1;
@@ -265,9 +268,11 @@ int f32_default_config(int64_t M, int64_t N, int64_t K) {
 
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
   switch (cfg) {
-    case 0: return f32::launch<128, 128, 32, 8, 8>(g, s);
-    case 1: return f32::launch<64, 64, 32, 4, 4>(g, s);
-    case 2: return f32::launch<128, 64, 32, 8, 4>(g, s);
+    case 0: return f32::launch<128, 128, 32, 8, 8, 1>(g, s);
+    case 1: return f32::launch<64, 64, 32, 4, 4, 1>(g, s);
+    case 2: return f32::launch<128, 64, 32, 8, 4, 1>(g, s);
+    case 3: return f32::launch<128, 128, 32, 8, 8, 2>(g, s);
+    case 4: return f32::launch<128, 64, 32, 8, 4, 2>(g, s);
     default: set_error("gemm_f32: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

@@ -233,10 +233,10 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t
 // bytes with an XOR swizzle of the 16-byte chunk index.
 template <int BM, int BN, int WM, int WN>
 struct Fp8Cfg {
-  static constexpr int NT = 256;
+  static constexpr int NT = 64 * (BM / WM) * (BN / WN);
   static constexpr int BK = 128;
   static constexpr int WAVES_N = BN / WN;
-  static_assert((BM / WM) * WAVES_N == 4, "4 waves");
+  static_assert((BM / WM) * WAVES_N == 4 || (BM / WM) * WAVES_N == 8, "4 or 8 waves");
   static constexpr int FM = WM / 32, FN = WN / 32;
   static constexpr int A_CH = BM * BK / 16 / NT;   // 16-byte chunks per lane per slab
   static constexpr int B_CH = BN * BK / 16 / NT;
@@ -247,7 +247,7 @@ struct Fp8Cfg {
 __device__ __forceinline__ int swz8(int r) { return (r ^ (r >> 3)) & 7; }
 
 template <int BM, int BN, int WM, int WN, bool BETA>
-__global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_kernel(
     int M, int N, int64_t Kp, float alpha, const uint8_t *__restrict__ qa,
     const uint8_t *__restrict__ qbT, const float *__restrict__ sa, const float *__restrict__ sb,
     float beta, float *__restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
@@ -361,11 +361,13 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(
   int t = 0;
   for (; t + 2 <= KT; t += 2) {
     gload(S0{}, kslab(t + 2));
+    __builtin_amdgcn_sched_barrier(0);
     mfma_step(0, 0);
     mfma_step(0, 1);
     sstore(S1{}, 1);
     __syncthreads();
     gload(S1{}, kslab(t + 3));
+    __builtin_amdgcn_sched_barrier(0);
     mfma_step(1, 0);
     mfma_step(1, 1);
     sstore(S0{}, 0);
@@ -374,6 +376,150 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(
   if (t < KT) {
     mfma_step(0, 0);
     mfma_step(0, 1);
+  }
+
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int col = wn0 + j * 32 + lrow;
+      if (col >= Nr) continue;
+      const float sj = sb[n0 + col] * alpha;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
+        if (row < Mr) {
+          float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
+          const float v = (sa[m0 + row] * sj) * acc[i][j][e];
+          *p = BETA ? fmaf(beta, *p, v) : v;
+        }
+      }
+    }
+}
+
+// Same tile, MFMA and epilogue, but the operand codes go from HBM straight
+// into LDS (buffer_load_dwordx4 ... lds): no register stage, so no VGPRs hold
+// slabs in flight and no VALU/LDS-store work sits between load and use.  A
+// wave's DMA writes 1024 contiguous LDS bytes (8 rows of 128 bytes, lane l at
+// byte 16 l); the swizzle is applied on the global side, i.e. the lane that
+// fills physical chunk p of row r fetches logical chunk p ^ swz8(r).  Two
+// separate LDS arrays hold the two stages.  Slab t+1 is in flight into one
+// stage while slab t is multiplied from the other; one barrier per slab,
+// preceded by a wait for the wave's own DMA.
+// 16 bytes per lane from a buffer resource into LDS at lds + 16 * lane (lds
+// must be wave-uniform).  The LDS address-space cast exists only in the device
+// pass; the host pass sees an empty body.
+__device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t rs, uint8_t *lds, int voffset) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)lds, 16,
+                                           voffset, 0, 0, 0);
+#endif
+}
+
+template <int BM, int BN, int WM, int WN, bool BETA>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_dma_kernel(
+    int M, int N, int64_t Kp, float alpha, const uint8_t *__restrict__ qa,
+    const uint8_t *__restrict__ qbT, const float *__restrict__ sa, const float *__restrict__ sb,
+    float beta, float *__restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+  using G = Fp8Cfg<BM, BN, WM, WN>;
+  constexpr int NW = G::NT / 64;
+  __shared__ __attribute__((aligned(1024))) uint8_t st0[G::STAGE];
+  __shared__ __attribute__((aligned(1024))) uint8_t st1[G::STAGE];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int Mr = M - m0, Nr = N - n0;
+  const int rowsA = Mr < BM ? Mr : BM, rowsB = Nr < BN ? Nr : BN;
+  // Rows past M (N) read as zero; they feed only C rows (columns) that are
+  // never stored.
+  const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(qa + (int64_t)m0 * Kp), (short)0, (int)(rowsA * Kp), kBufferFlags);
+  const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(qbT + (int64_t)n0 * Kp), (short)0, (int)(rowsB * Kp), kBufferFlags);
+  // DMA block d (1024 bytes) covers stage rows 8d..8d+7; block d of A is
+  // issued by wave d % NW as its (d / NW)-th A load.
+  int voA[G::A_CH], voB[G::B_CH];
+#pragma unroll
+  for (int i = 0; i < G::A_CH; ++i) {
+    const int r = (i * NW + wave) * 8 + (lane >> 3);
+    voA[i] = r * (int)Kp + (((lane & 7) ^ swz8(r)) << 4);
+  }
+#pragma unroll
+  for (int i = 0; i < G::B_CH; ++i) {
+    const int r = (i * NW + wave) * 8 + (lane >> 3);
+    voB[i] = r * (int)Kp + (((lane & 7) ^ swz8(r)) << 4);
+  }
+  auto dma = [&](uint8_t *stage, int k0) {
+#pragma unroll
+    for (int i = 0; i < G::A_CH; ++i) lds_load16(rsA, stage + (i * NW + wave) * 1024, voA[i] + k0);
+#pragma unroll
+    for (int i = 0; i < G::B_CH; ++i)
+      lds_load16(rsB, stage + BM * G::BK + (i * NW + wave) * 1024, voB[i] + k0);
+  };
+
+  const int wm0 = (wave / G::WAVES_N) * WM, wn0 = (wave % G::WAVES_N) * WN;
+  const int lrow = lane & 31, lgrp = lane >> 5;
+  f32x16 acc[G::FM][G::FN];
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+  auto mfma_step = [&](const uint8_t *sA, int ks) {
+    const uint8_t *sB = sA + BM * G::BK;
+    const int c0 = ks * 4 + lgrp * 2;
+    i32x8 a[G::FM], b[G::FN];
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i) {
+      const int r = wm0 + i * 32 + lrow;
+      const uint4 lo = *reinterpret_cast<const uint4 *>(sA + r * G::BK + ((c0 ^ swz8(r)) << 4));
+      const uint4 hi = *reinterpret_cast<const uint4 *>(sA + r * G::BK + (((c0 + 1) ^ swz8(r)) << 4));
+      a[i] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int r = wn0 + j * 32 + lrow;
+      const uint4 lo = *reinterpret_cast<const uint4 *>(sB + r * G::BK + ((c0 ^ swz8(r)) << 4));
+      const uint4 hi = *reinterpret_cast<const uint4 *>(sB + r * G::BK + (((c0 + 1) ^ swz8(r)) << 4));
+      b[j] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                     0, 0, 0, 0);
+  };
+
+  // Loads past the last slab are clamped to it: in-bounds, never consumed.
+  const int KT = (int)(Kp / G::BK);
+  auto kslab = [&](int sl) { return (sl < KT ? sl : KT - 1) * G::BK; };
+  dma(st0, 0);
+  int t = 0;
+  for (; t + 2 <= KT; t += 2) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's DMA of slab t has landed
+    __syncthreads();                // ... and every wave's; stage 1 is free
+    dma(st1, kslab(t + 1));
+    __builtin_amdgcn_sched_barrier(0);  // keep the DMA issue ahead of the MFMAs
+    mfma_step(st0, 0);
+    mfma_step(st0, 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    dma(st0, kslab(t + 2));
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step(st1, 0);
+    mfma_step(st1, 1);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (t < KT) {
+    mfma_step(st0, 0);
+    mfma_step(st0, 1);
   }
 
 #pragma unroll
@@ -462,28 +608,57 @@ gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, in
   return GEMM_STATUS_OK;
 }
 
-gemm_status fp8_gemm_run(int64_t M, int64_t N, int64_t K, float alpha, const void *ws, float beta,
-                         float *C, int64_t ldc, hipStream_t s) {
-  const fp8::Layout L = fp8::layout(M, N, K);
-  const uint8_t *base = static_cast<const uint8_t *>(ws);
-  constexpr int BM = 256, BN = 256;
-  if ((int64_t)BM * L.Kp >= ((int64_t)1 << 31)) {
+template <int BM, int BN, int WM, int WN, bool DMA>
+static gemm_status fp8_launch(int64_t M, int64_t N, const fp8::Layout &L, float alpha,
+                              const uint8_t *base, float beta, float *C, int64_t ldc,
+                              hipStream_t s) {
+  if ((int64_t)(BM > BN ? BM : BN) * L.Kp >= ((int64_t)1 << 31)) {
     set_error("gemm_fp8: K too large for 32-bit tile offsets");
     return GEMM_STATUS_UNSUPPORTED;
   }
   const int tiles_m = (int)((M + BM - 1) / BM), tiles_n = (int)((N + BN - 1) / BN);
-  const dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(256);
+  const dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(64 * (BM / WM) * (BN / WN));
   const uint8_t *qa = base + L.qa, *qb = base + L.qb;
   const float *sa = reinterpret_cast<const float *>(base + L.sa);
   const float *sb = reinterpret_cast<const float *>(base + L.sb);
+  if (DMA) {
+    if (beta != 0.0f)
+      hipLaunchKernelGGL((fp8::gemm_fp8_dma_kernel<BM, BN, WM, WN, true>), grid, block, 0, s,
+                         (int)M, (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
+    else
+      hipLaunchKernelGGL((fp8::gemm_fp8_dma_kernel<BM, BN, WM, WN, false>), grid, block, 0, s,
+                         (int)M, (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
+    return check_launch("gemm_fp8_dma_kernel");
+  }
   if (beta != 0.0f)
-    hipLaunchKernelGGL((fp8::gemm_fp8_kernel<BM, BN, 128, 128, true>), grid, block, 0, s, (int)M,
+    hipLaunchKernelGGL((fp8::gemm_fp8_kernel<BM, BN, WM, WN, true>), grid, block, 0, s, (int)M,
                        (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((fp8::gemm_fp8_kernel<BM, BN, 128, 128, false>), grid, block, 0, s, (int)M,
+    hipLaunchKernelGGL((fp8::gemm_fp8_kernel<BM, BN, WM, WN, false>), grid, block, 0, s, (int)M,
                        (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
   return check_launch("gemm_fp8_kernel");
 }
+
+int fp8_num_configs() { return 3; }
+const char *fp8_config_name(int cfg) {
+  switch (cfg) {
+    case 0: return "fp8_256x256x128_8w128x64";
+    case 1: return "fp8_256x256x128_4w128x128";
+    default: return "fp8_256x256x128_8w128x64_dma";
+  }
+}
+
+gemm_status fp8_gemm_run_cfg(int64_t M, int64_t N, int64_t K, float alpha, const void *ws,
+                             float beta, float *C, int64_t ldc, int cfg, hipStream_t s) {
+  const fp8::Layout L = fp8::layout(M, N, K);
+  const uint8_t *base = static_cast<const uint8_t *>(ws);
+  if (cfg == 1) return fp8_launch<256, 256, 128, 128, false>(M, N, L, alpha, base, beta, C, ldc, s);
+  if (cfg == 2) return fp8_launch<256, 256, 128, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
+  return fp8_launch<256, 256, 128, 64, false>(M, N, L, alpha, base, beta, C, ldc, s);
+}
+
+// The direct-to-LDS kernel is the fastest at every measured shape.
+int fp8_default_config(int64_t, int64_t, int64_t) { return 2; }
 
 gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s) {
   const int64_t want = (n + 255) / 256;

@@ -44,31 +44,54 @@ __device__ __forceinline__ void run_tile(const Desc &d, int m0, int n0, __bf16 *
                                                    d.beta, d.C, d.ldc, m0, n0, lds);
 }
 
+__device__ __forceinline__ int starts_at(bool in_lds, const int *s_starts, const int *starts,
+                                         int p) {
+  return in_lds ? s_starts[p] : starts[p];
+}
+
 __global__ __launch_bounds__(64) void clear_counter_kernel(unsigned *counter) {
   if (threadIdx.x == 0) counter[0] = 0u;
 }
+
+// Tile prefixes of batches up to this size are searched in LDS.
+constexpr int kLdsStarts = 2048;
 
 __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict__ descs,
                                                          const int *__restrict__ starts, int count,
                                                          int total_tiles,
                                                          unsigned *__restrict__ counter) {
   __shared__ __attribute__((aligned(16))) __bf16 lds[kLdsBytes / 2];
-  __shared__ int s_tile;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int t = s_tile;
-    __syncthreads();
-    if (t >= total_tiles) break;
+  __shared__ int s_starts[kLdsStarts];
+  __shared__ int s_tile[2];
+  const bool in_lds = count < kLdsStarts;
+  if (in_lds)
+    for (int i = threadIdx.x; i <= count; i += 256) s_starts[i] = starts[i];
+  if (threadIdx.x == 0) s_tile[0] = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  int t = s_tile[0];
+  for (int it = 1; t < total_tiles; ++it) {
+    // Dequeue the next tile now: the atomic's round trip overlaps this tile's
+    // work, and its result is only read after the tile.
+    unsigned next = 0u;
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
     // owning problem: the last p with starts[p] <= t
     int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (starts[mid] <= t) lo = mid;
-      else hi = mid - 1;
+    if (in_lds) {
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_starts[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+    } else {
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);
     const Desc d = descs[lo];
-    const int local = t - starts[lo];
+    const int local = t - starts_at(in_lds, s_starts, starts, lo);
     const int bm = d.variant == 0 ? 128 : 64, bn = bm;
     const int m0 = (local / d.tiles_n) * bm, n0 = (local % d.tiles_n) * bn;
     const int sel = d.variant * 4 + (d.vec ? 2 : 0) + (d.beta != 0.0f ? 1 : 0);
@@ -82,6 +105,12 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
       case 6: run_tile<1, true, false>(d, m0, n0, lds); break;
       default: run_tile<1, true, true>(d, m0, n0, lds); break;
     }
+    // One barrier per tile: publishes the next index (alternate slots, so no
+    // thread can still be reading the slot being written) and separates this
+    // tile's last LDS reads from the next tile's first LDS writes.
+    if (threadIdx.x == 0) s_tile[it & 1] = (int)next;
+    __syncthreads();
+    t = s_tile[it & 1];
   }
 }
 

@@ -42,8 +42,11 @@ size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K);
 int64_t fp8_kp(int64_t K);
 gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
                              const float *B, int64_t ldb, void *ws, hipStream_t s);
-gemm_status fp8_gemm_run(int64_t M, int64_t N, int64_t K, float alpha, const void *ws, float beta,
-                         float *C, int64_t ldc, hipStream_t s);
+int fp8_num_configs();
+int fp8_default_config(int64_t M, int64_t N, int64_t K);
+const char *fp8_config_name(int cfg);
+gemm_status fp8_gemm_run_cfg(int64_t M, int64_t N, int64_t K, float alpha, const void *ws,
+                             float beta, float *C, int64_t ldc, int cfg, hipStream_t s);
 gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s);
 
 // Autotuner table: the tuned configuration for this size bucket, or -1.

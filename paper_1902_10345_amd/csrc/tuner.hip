@@ -34,20 +34,21 @@ int bucket(int64_t x) {
   return b;
 }
 Key key(int path, int np, int64_t M, int64_t N, int64_t K) {
+  if (path == GEMM_PATH_FP8_PREQUANTIZED) path = GEMM_PATH_FP8;  // same kernels
   return Key(path, path == GEMM_PATH_3XBF16 ? np : 0, bucket(M), bucket(N), bucket(K));
 }
 const char *cfg_name(int path, int cfg) {
   switch (path) {
     case GEMM_PATH_F32: return f32_config(cfg).name;
     case GEMM_PATH_3XBF16: return bx3_config(cfg).name;
-    default: return "fp8_256x256x128_w128x128";
+    default: return fp8_config_name(cfg);
   }
 }
 int cfg_count(int path) {
   switch (path) {
     case GEMM_PATH_F32: return f32_num_configs();
     case GEMM_PATH_3XBF16: return bx3_num_configs();
-    default: return 1;
+    default: return fp8_num_configs();
   }
 }
 }  // namespace
@@ -80,7 +81,7 @@ gemm_status gemm_autotune(int path, int64_t M, int64_t N, int64_t K, float alpha
                           hipStream_t stream, int *best_cfg) {
   clear_error();
   const char *fn = "gemm_autotune";
-  if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8) return bad_arg(1, fn, "(path) unknown");
+  if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8_PREQUANTIZED) return bad_arg(1, fn, "(path) unknown");
   if (reps < 1) return bad_arg(16, fn, "(reps) must be >= 1");
   if (!best_cfg) return bad_arg(18, fn, "(best_cfg) is NULL");
   hipEvent_t e0, e1;

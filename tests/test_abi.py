@@ -89,8 +89,30 @@ def test_err_norm_argument_codes():
 
 def test_configs_have_names():
     import paper_1902_10345_amd as mm
-    for path in (mm.PATH_F32,):
+    for path in (mm.PATH_F32, mm.PATH_3XBF16, mm.PATH_FP8, mm.PATH_FP8_PREQUANTIZED):
         n = mm.gemm_num_configs(path)
         assert n >= 1
         names = [mm.gemm_config_name(path, i) for i in range(n)]
         assert all(names) and len(set(names)) == n
+    # the two FP8 paths run the same kernels
+    assert [mm.gemm_config_name(mm.PATH_FP8, i) for i in range(mm.gemm_num_configs(mm.PATH_FP8))] == \
+        [mm.gemm_config_name(mm.PATH_FP8_PREQUANTIZED, i)
+         for i in range(mm.gemm_num_configs(mm.PATH_FP8_PREQUANTIZED))]
+    assert mm.gemm_num_configs(4) == 0 and mm.gemm_config_name(4, 0) == ""
+
+
+def test_prequantized_run_config_argument_codes():
+    """GEMM_PATH_FP8_PREQUANTIZED ignores A, B, lda and ldb."""
+    import paper_1902_10345_amd as mm
+    lib, P = mm.lib, mm.PATH_FP8_PREQUANTIZED
+    nb = mm.gemm_fp8_workspace_bytes(4, 4, 4)
+    assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, None, nb, None) == -15
+    assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 8, nb, None) == -15
+    assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 256, nb - 1, None) == -16
+    assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 3, 3, 256, nb, None) == -13
+    assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, None, 4, 3, 256, nb, None) == -12
+    assert lib.gemm_run_config(P, 0, -1, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 256, nb, None) == -3
+    assert lib.gemm_run_config(P, 3, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 256, nb, None) == -2
+    # M == 0: nothing to do, nothing touched
+    assert lib.gemm_run_config(P, 0, 0, 4, 4, 1.0, None, 0, None, 0, 0.0, None, 4, 3, 256,
+                               mm.gemm_fp8_workspace_bytes(0, 4, 4), None) == 0

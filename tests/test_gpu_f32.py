@@ -58,12 +58,12 @@ def test_parity_shapes(M, N, K, alpha, beta):
     _check(A, B, C0, C, alpha, beta)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2])
-def test_every_config(cfg):
+def test_every_config():
     import paper_1902_10345_amd as mm
     M, N, K = 300, 260, 130
-    A, B, C0, _, C = _run(mm, M, N, K, 1.5, 0.5, seed=11, cfg=cfg)
-    _check(A, B, C0, C, 1.5, 0.5)
+    for cfg in range(mm.gemm_num_configs(mm.PATH_F32)):
+        A, B, C0, _, C = _run(mm, M, N, K, 1.5, 0.5, seed=11, cfg=cfg)
+        _check(A, B, C0, C, 1.5, 0.5)
 
 
 def test_padded_leading_dimensions_and_untouched_padding():
