@@ -46,6 +46,30 @@ def _dev_inputs(M, N, K, seed, torch):
     return (A, B, C0), tuple(torch.from_numpy(x).cuda() for x in (A, B, C0))
 
 
+def _sclk_mhz():
+    """The engine clock's current DPM level from sysfs (None if unreadable).
+    Under MFMA load the power limit holds the clock below its 2.4 GHz peak."""
+    import glob
+    for f in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            for line in open(f):
+                if "*" in line:
+                    return int("".join(ch for ch in line.split(":")[1] if ch.isdigit()))
+        except (OSError, ValueError, IndexError):
+            continue
+    return None
+
+
+def _settle(fn, seconds, torch):
+    """Run fn untimed for about `seconds`: the engine clock ramps up over
+    roughly a second of sustained load, longer than the warm-up steps."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+
+
 def _time_steps(fn, steps, warmup, torch):
     """Run `fn` warmup times, then time exactly `steps` calls on the current
     stream.  Returns (ms_per_step from the block, per-step list in ms)."""
@@ -262,6 +286,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--settle-seconds", type=float, default=1.0,
+                    help="untimed run of the headline GEMM before its warm-up (clock ramp)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline GEMM (for kernel-trace profiles)")
     args = ap.parse_args()
@@ -285,8 +311,10 @@ def main():
     flops = 2.0 * M * N * K
     (hA, hB, hC0), (A, B, C) = _dev_inputs(M, N, K, 2, torch)
     _log("headline: gemm_f32_3xbf16 %dx%dx%d n_products=3" % (M, N, K))
-    ms, per, wall = _time_steps(
-        lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, C, N, 3), K_, W_, torch)
+    head = lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, C, N, 3)  # noqa: E731
+    _settle(head, args.settle_seconds, torch)
+    ms, per, wall = _time_steps(head, K_, W_, torch)
+    sclk = _sclk_mhz()
     head_tflops = flops / (ms * 1e-3) / 1e12
     paths["3xbf16_n3_4096^3"] = {"ms": round(ms, 4), "tflops": round(head_tflops, 1),
                                 "frac_bf16_peak": round(head_tflops / PEAK_BF16_MFMA, 4),
@@ -419,6 +447,8 @@ def main():
         "serving": serving,
         "accuracy": accuracy,
         "wall_s_timed_region": round(wall, 3),
+        "settle_s_before_warmup": args.settle_seconds,
+        "sclk_dpm_mhz_after_timed": sclk,
     }
     print(json.dumps(line), flush=True)
 

@@ -77,6 +77,10 @@ struct Cfg {
   static constexpr int PLANE_B = BN * BK;
   static constexpr int STAGE = NP * (PLANE_A + PLANE_B);  // bf16 per stage
   static constexpr int LDS_BYTES = 2 * STAGE * 2;
+  // Register sets for slabs in flight: with BK >= 32 one slab's MFMA work
+  // (2 k-steps) already covers the load latency, so one set is kept and the
+  // registers go to fragments; BK = 16 keeps two sets.
+  static constexpr int SETS = BK >= 32 ? 1 : 2;
 };
 
 // One output tile.  lds must hold Cfg::LDS_BYTES bytes (16-byte aligned).
@@ -112,22 +116,22 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
     const int idx = tid + NT * i;
     a_voff[i] = ((idx / CH) * (int)lda + (idx % CH) * 8) * 4;
   }
-  // byte offsets of this lane's 8 B elements per item inside a full slab
-  // (relative to the slab's first row); columns past N get an offset beyond
-  // any slab resource, so they read as zero
-  int b_voff[G::B_ITEMS][8];
+  // B items: this lane's column (a byte offset inside a slab row; columns
+  // past N get an offset beyond any slab resource, so they read as zero) and
+  // the item's first row of the slab (wave-uniform, a scalar offset)
+  int b_vcol[G::B_ITEMS], b_srow[G::B_ITEMS];
+  const int ldb4 = (int)ldb * 4;
 #pragma unroll
   for (int i = 0; i < G::B_ITEMS; ++i) {
     const int idx = tid + NT * i;
-    const int n = idx % BN, c = idx / BN;
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      b_voff[i][e] = n < colsB ? ((8 * c + e) * (int)ldb + n) * 4 : (int)0x80000000;
+    const int n = idx % BN;
+    b_vcol[i] = n < colsB ? n * 4 : (int)0x80000000;
+    b_srow[i] = __builtin_amdgcn_readfirstlane(8 * (idx / BN)) * ldb4;
   }
 
   // ---- global -> registers (two register sets, selected at compile time) --
-  float ra[2][G::A_ITEMS][8];
-  float rb[2][G::B_ITEMS][8];
+  float ra[G::SETS][G::A_ITEMS][8];
+  float rb[G::SETS][G::B_ITEMS][8];
   // FAST: every element of the slab lies in [0, K) (or the data is never
   // consumed).  Otherwise elements outside [0, K) read as zero.
   auto gload = [&](auto S, auto F, int k0) {
@@ -175,7 +179,7 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           rb[set][i][e] = __builtin_bit_cast(
-              float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, b_voff[i][e], 0, 0));
+              float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, b_vcol[i], b_srow[i] + e * ldb4, 0));
     } else {
 #pragma unroll
       for (int i = 0; i < G::B_ITEMS; ++i) {
@@ -249,67 +253,90 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
-  auto mfma_step = [&](int stage, int ks) {
+  // Fragments of one 16-deep k-step: the lane's 8 consecutive k of its A row
+  // (per block i and plane p) and of its B column (per block j and plane p).
+  struct Frags {
+    bf16x8 a[NP][G::FM], b[NP][G::FN];
+  };
+  // Reads in the order the products consume them (b0 and a1 first).
+  auto frag_read = [&](Frags &f, int stage, int ks) {
     const __bf16 *sA = lds + stage * G::STAGE;
     const __bf16 *sB = sA + NP * G::PLANE_A;
     const int c = ks * 2 + lgrp;  // logical 16-byte chunk of this lane
-    bf16x8 a[NP][G::FM], b[NP][G::FN];
+    auto rd_b = [&](int p) {
 #pragma unroll
-    for (int i = 0; i < G::FM; ++i) {
-      const int r = wm0 + i * 32 + lrow;
-      const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
+      for (int j = 0; j < G::FN; ++j) {
+        const int n = wn0 + j * 32 + lrow;
+        f.b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + n * BK +
+                                                      ((c ^ swz<BK>(n)) << 3));
+      }
+    };
+    auto rd_a = [&](int p) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p) a[p][i] = *reinterpret_cast<const bf16x8 *>(sA + p * G::PLANE_A + off);
-    }
+      for (int i = 0; i < G::FM; ++i) {
+        const int r = wm0 + i * 32 + lrow;
+        f.a[p][i] = *reinterpret_cast<const bf16x8 *>(sA + p * G::PLANE_A + r * BK +
+                                                      ((c ^ swz<BK>(r)) << 3));
+      }
+    };
+    rd_b(0);
+    if constexpr (NP == 3) rd_a(2);
+    rd_a(1);
+    rd_b(1);
+    if constexpr (NP == 3) rd_b(2);
+    rd_a(0);
+  };
+  // Small products first, the leading product last; consecutive MFMAs go to
+  // different accumulator blocks.
+  auto frag_mfma = [&](const Frags &f) {
+    auto prod = [&](int pa, int pb) {
 #pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const int n = wn0 + j * 32 + lrow;
-      const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
+      for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-      for (int p = 0; p < NP; ++p) b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + off);
-    }
-    // Small products first, the leading product last; consecutive MFMAs go
-    // to different accumulator blocks.
+        for (int j = 0; j < G::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[pa][i], f.b[pb][j], acc[i][j],
+                                                              0, 0, 0);
+    };
     if constexpr (NP == 3) {
-#pragma unroll
-      for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+      prod(2, 0);
+      prod(1, 1);
+      prod(0, 2);
     }
+    prod(1, 0);
+    prod(0, 1);
+    prod(0, 0);
+  };
+  // All MFMAs of one LDS stage.  With one k-step per stage every fragment
+  // read is issued before the first MFMA (a scheduling barrier stops the
+  // compiler from re-reading fragments in small groups, each waiting out the
+  // LDS latency).  With two k-steps the registers do not allow both steps'
+  // fragments at once; each step reads, then multiplies, and the compiler
+  // overlaps the second step's reads with the first step's MFMAs.
+  auto mfma_stage = [&](int stage) {
+    if constexpr (G::KS == 1) {
+      Frags f0;
+      frag_read(f0, stage, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      frag_mfma(f0);
+    } else {
 #pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int j = 0; j < G::FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int j = 0; j < G::FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int j = 0; j < G::FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+      for (int ks = 0; ks < G::KS; ++ks) {
+        Frags f;
+        frag_read(f, stage, ks);
+        frag_mfma(f);
+      }
+    }
   };
 
   // ---- K loop ---------------------------------------------------------------
-  // Slab t is multiplied from LDS stage t%2 while (a) the global loads of slab
-  // t+2 are in flight into one register set and (b) slab t+1, loaded during
-  // slab t-1 into the other set, is split and written to stage (t+1)%2.  Both
-  // are independent of slab t's MFMAs, so the scheduler interleaves them; one
-  // barrier per slab separates the LDS stages.
+  // Two register sets (BK = 16): slab t is multiplied from LDS stage t%2 while
+  // (a) the global loads of slab t+2 are in flight into one register set and
+  // (b) slab t+1, loaded during slab t-1 into the other set, is split and
+  // written to stage (t+1)%2.  One register set (BK >= 32): slab t+1 is
+  // loaded at the top of slab t's step and split and written at its end.
+  // Either way the loads are issued ahead of the MFMAs (a scheduling barrier
+  // keeps the compiler from sinking them) and one barrier per slab separates
+  // the LDS stages.
   // The slab grid ends exactly at K (slab s covers [kbase + s*BK, +BK) with
   // kbase = K - KT*BK <= 0), so only slab 0 can be partial; it is loaded with
   // masking in the prologue.  Loads past the last slab are clamped to it
@@ -325,27 +352,42 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   auto kslab = [&](int sl) { return kbase + (sl < KT ? sl : KT - 1) * BK; };
   gload(S0{}, Masked{}, kbase);
   sstore(S0{}, 0);
-  if (KT > 1) gload(S1{}, Fast{}, kslab(1));
-  else gload(S1{}, Masked{}, kbase);
-  __syncthreads();
   int t = 0;
-  for (; t + 2 <= KT; t += 2) {
-    gload(S0{}, Fast{}, kslab(t + 2));
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int ks = 0; ks < G::KS; ++ks) mfma_step(0, ks);
-    sstore(S1{}, 1);
+  if constexpr (G::SETS == 1) {
+    // One register set: slab t+1 is loaded at the top of the step that
+    // multiplies slab t and written to the other stage at its end.
     __syncthreads();
-    gload(S1{}, Fast{}, kslab(t + 3));
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int ks = 0; ks < G::KS; ++ks) mfma_step(1, ks);
-    sstore(S0{}, 0);
+    for (; t + 2 <= KT; t += 2) {
+      gload(S0{}, Fast{}, kslab(t + 1));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_stage(0);
+      sstore(S0{}, 1);
+      __syncthreads();
+      gload(S0{}, Fast{}, kslab(t + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_stage(1);
+      sstore(S0{}, 0);
+      __syncthreads();
+    }
+  } else {
+    if (KT > 1) gload(S1{}, Fast{}, kslab(1));
+    else gload(S1{}, Masked{}, kbase);
     __syncthreads();
+    for (; t + 2 <= KT; t += 2) {
+      gload(S0{}, Fast{}, kslab(t + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_stage(0);
+      sstore(S1{}, 1);
+      __syncthreads();
+      gload(S1{}, Fast{}, kslab(t + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_stage(1);
+      sstore(S0{}, 0);
+      __syncthreads();
+    }
   }
   if (t < KT) {  // odd slab count: the last slab sits in stage 0
-#pragma unroll
-    for (int ks = 0; ks < G::KS; ++ks) mfma_step(0, ks);
+    mfma_stage(0);
   }
 
   // ---- peeled epilogue ----------------------------------------------------
