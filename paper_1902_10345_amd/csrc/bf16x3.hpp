@@ -370,19 +370,44 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       __syncthreads();
     }
   } else {
+    // Two register sets, one k-step per stage: each step's instructions are
+    // interleaved one by one with its MFMAs -- all fragment reads first, then
+    // one global load after each of the first MFMAs, then the split's VALU
+    // work a few instructions per MFMA, the LDS writes last.  Issued in
+    // clusters, the loads and the split stall the wave between MFMAs (both
+    // waves of a SIMD reach them together, so neither feeds the pipe).
+    static_assert(G::KS == 1, "two register sets are used with 16-deep slabs");
+    constexpr int kMfma = G::FM * G::FN * (NP == 2 ? 3 : 6);
+    constexpr int kReads = (G::FM + G::FN) * NP;
+    constexpr int kLoads = G::A_ITEMS * (VEC ? 2 : 8) + G::B_ITEMS * 8;
+    constexpr int kWrites = (G::A_ITEMS + G::B_ITEMS) * NP;
+    constexpr int kLoadSlots = kLoads < kMfma ? kLoads : kMfma;
+    auto step = [&](auto LS, int kload, int mstage, auto SS, int sstage) {
+      gload(LS, Fast{}, kload);
+      Frags f;
+      frag_read(f, mstage, 0);
+      frag_mfma(f);
+      sstore(SS, sstage);
+      __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);   // DS read
+#pragma unroll
+      for (int i = 0; i < kLoadSlots; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);      // VMEM read
+      }
+#pragma unroll
+      for (int i = kLoadSlots; i < kMfma; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);      // VALU
+      }
+      __builtin_amdgcn_sched_group_barrier(0x200, kWrites, 0);  // DS write
+    };
     if (KT > 1) gload(S1{}, Fast{}, kslab(1));
     else gload(S1{}, Masked{}, kbase);
     __syncthreads();
     for (; t + 2 <= KT; t += 2) {
-      gload(S0{}, Fast{}, kslab(t + 2));
-      __builtin_amdgcn_sched_barrier(0);
-      mfma_stage(0);
-      sstore(S1{}, 1);
+      step(S0{}, kslab(t + 2), 0, S1{}, 1);
       __syncthreads();
-      gload(S1{}, Fast{}, kslab(t + 3));
-      __builtin_amdgcn_sched_barrier(0);
-      mfma_stage(1);
-      sstore(S0{}, 0);
+      step(S1{}, kslab(t + 3), 1, S0{}, 0);
       __syncthreads();
     }
   }
