@@ -112,7 +112,8 @@ def test_prequantized_run_config_argument_codes():
     assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 3, 3, 256, nb, None) == -13
     assert lib.gemm_run_config(P, 0, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, None, 4, 3, 256, nb, None) == -12
     assert lib.gemm_run_config(P, 0, -1, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 256, nb, None) == -3
-    assert lib.gemm_run_config(P, 3, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 256, nb, None) == -2
+    n = mm.gemm_num_configs(P)
+    assert lib.gemm_run_config(P, n, 4, 4, 4, 1.0, None, 0, None, 0, 0.0, F, 4, 3, 256, nb, None) == -2
     # M == 0: nothing to do, nothing touched
     assert lib.gemm_run_config(P, 0, 0, 4, 4, 1.0, None, 0, None, 0, 0.0, None, 4, 3, 256,
                                mm.gemm_fp8_workspace_bytes(0, 4, 4), None) == 0
