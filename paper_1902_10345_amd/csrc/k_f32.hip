@@ -259,11 +259,13 @@ const TileConfig &f32_config(int i) { return kF32Configs[i]; }
 
 int f32_default_config(int64_t M, int64_t N, int64_t K) {
   (void)K;
+  // measured: a tile shape wins while it gives every CU at least two tiles
+  const int64_t cus = num_cus();
   const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-  if (big >= 2 * (int64_t)num_cus()) return 3;  // 128 x 128, k loop unrolled by 2
+  if (big >= 2 * cus) return 3;  // 128 x 128, k loop unrolled by 2
   const int64_t mid = ((M + 127) / 128) * ((N + 63) / 64);
-  if (mid >= (int64_t)num_cus()) return 2;
-  return 1;
+  if (mid >= 2 * cus) return 4;  // 128 x 64, unrolled by 2
+  return 1;                       // 64 x 64
 }
 
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
