@@ -382,7 +382,24 @@ def main():
         one("3xbf16_n3_512x4096x4096_row_shard",
             lambda: mm.gemm_f32_3xbf16(M5, N, K, 1.5, A5, K, B5, N, 0.5, C5, N, 3),
             2.0 * M5 * N * K, PEAK_BF16_MFMA, "bf16_peak")
+        nb5 = mm.gemm_splitk_workspace_bytes(M5, N, K, 0)
+        ws5 = torch.empty(max(nb5, 256), dtype=torch.uint8, device="cuda")
+        one("3xbf16_n3_512x4096x4096_row_shard_splitk%d" % mm.gemm_splitk_default_splits(M5, N, K),
+            lambda: mm.gemm_f32_3xbf16_splitk(M5, N, K, 1.5, A5, K, B5, N, 0.5, C5, N, 3, 0, ws5, nb5),
+            2.0 * M5 * N * K, PEAK_BF16_MFMA, "bf16_peak")
         del A5, B5, C5
+        # a skinny product: 16 output tiles of 128 x 128, the reduction split 16 ways
+        M6 = 64
+        _, (A6, B6, C6) = _dev_inputs(M6, N, K, 9, torch)
+        one("3xbf16_n3_64x4096x4096",
+            lambda: mm.gemm_f32_3xbf16(M6, N, K, 1.5, A6, K, B6, N, 0.5, C6, N, 3),
+            2.0 * M6 * N * K, PEAK_BF16_MFMA, "bf16_peak")
+        nb6 = mm.gemm_splitk_workspace_bytes(M6, N, K, 0)
+        ws6 = torch.empty(max(nb6, 256), dtype=torch.uint8, device="cuda")
+        one("3xbf16_n3_64x4096x4096_splitk%d" % mm.gemm_splitk_default_splits(M6, N, K),
+            lambda: mm.gemm_f32_3xbf16_splitk(M6, N, K, 1.5, A6, K, B6, N, 0.5, C6, N, 3, 0, ws6, nb6),
+            2.0 * M6 * N * K, PEAK_BF16_MFMA, "bf16_peak")
+        del A6, B6, C6, ws5, ws6
 
     grouped = None
     if not args.no_grouped:

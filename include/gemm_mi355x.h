@@ -88,6 +88,35 @@ gemm_status gemm_f32_3xbf16(int64_t M, int64_t N, int64_t K, float alpha,
                             float beta, float *C, int64_t ldc, int n_products,
                             hipStream_t stream);
 
+/* Split-K form of gemm_f32_3xbf16, for shapes whose output tiles alone leave
+ * compute units idle (few or thin tiles, deep K).  The reduction over k is cut
+ * into `splits` chunks of whole 16-deep (32-deep for 6 products) slabs; each
+ * (chunk, 128 x 128 output tile) pair is one workgroup that writes its partial
+ * product to the workspace, and a second kernel resolves the write conflict of
+ * the chunks on C -- the write-conflict resolution of a reduction (Sec. 3.3,
+ * write-conflict resolution memlets; App. A, the wcr attribute), here an
+ * ordered sum rather than atomics -- by summing them in chunk order and applying
+ * alpha and beta (C <- alpha * sum_c P_c + beta * C; beta == 0: C is not
+ * read).  Deterministic for a given (shape, n_products, splits); with one
+ * chunk the result equals that of the 128 x 128 tile configuration
+ * (gemm_run_config, configuration "bx3_128x128x16_4w64x64_p3" or
+ * "bx3_128x128x32_4w64x64_p6") bit for bit.
+ * splits: 1..64, or 0 for gemm_splitk_default_splits (enough chunks for two
+ * workgroups per compute unit, each chunk at least 256 deep).
+ * workspace: device memory of at least gemm_splitk_workspace_bytes(M, N, K,
+ * splits) bytes (splits * M * N floats; 0 bytes, and NULL allowed, when the
+ * split count resolves to 1), 256-byte aligned, owned by the caller.
+ * Arguments: 1..11 as gemm_f32, 12 n_products, 13 splits, 14 workspace,
+ * 15 ws_bytes, 16 stream.  Returns -14 / -15 for a missing, misaligned or
+ * short workspace. */
+int gemm_splitk_default_splits(int64_t M, int64_t N, int64_t K);
+size_t gemm_splitk_workspace_bytes(int64_t M, int64_t N, int64_t K, int splits);
+gemm_status gemm_f32_3xbf16_splitk(int64_t M, int64_t N, int64_t K, float alpha,
+                                   const float *A, int64_t lda, const float *B, int64_t ldb,
+                                   float beta, float *C, int64_t ldc, int n_products,
+                                   int splits, void *workspace, size_t ws_bytes,
+                                   hipStream_t stream);
+
 /* The staging split alone, for verification: x (n floats, device) ->
  * planes p0, p1, p2 (n bfloat16 bit patterns each, device; p2 may be NULL).
  * Arguments: 1 n, 2 x, 3 p0, 4 p1, 5 p2, 6 stream. */

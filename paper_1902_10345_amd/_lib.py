@@ -61,6 +61,10 @@ _sig("gemm_version", ctypes.c_char_p)
 _sig("gemm_f32", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _vp)
 _sig("gemm_f32_3xbf16", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _int,
      _vp)
+_sig("gemm_splitk_default_splits", _int, _i64, _i64, _i64)
+_sig("gemm_splitk_workspace_bytes", _sz, _i64, _i64, _i64, _int)
+_sig("gemm_f32_3xbf16_splitk", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64,
+     _int, _int, _vp, _sz, _vp)
 _sig("split_bf16x3", _int, _i64, _vp, _vp, _vp, _vp, _vp)
 _sig("gemm_fp8_workspace_bytes", _sz, _i64, _i64, _i64)
 _sig("gemm_fp8_scaled", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _vp,
@@ -157,6 +161,21 @@ def gemm_f32(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
 def gemm_f32_3xbf16(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products=3, stream=None):
     return check(lib.gemm_f32_3xbf16(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
                                      n_products, stream_handle(stream)))
+
+
+def gemm_splitk_default_splits(M, N, K) -> int:
+    return int(lib.gemm_splitk_default_splits(M, N, K))
+
+
+def gemm_splitk_workspace_bytes(M, N, K, splits=0) -> int:
+    return int(lib.gemm_splitk_workspace_bytes(M, N, K, splits))
+
+
+def gemm_f32_3xbf16_splitk(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products=3, splits=0,
+                           workspace=None, ws_bytes=0, stream=None):
+    return check(lib.gemm_f32_3xbf16_splitk(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C),
+                                            ldc, n_products, splits, ptr(workspace), ws_bytes,
+                                            stream_handle(stream)))
 
 
 def split_bf16x3(n, x, p0, p1, p2=None, stream=None):

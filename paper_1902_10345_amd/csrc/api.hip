@@ -125,6 +125,40 @@ gemm_status gemm_f32_3xbf16(int64_t M, int64_t N, int64_t K, float alpha, const 
   return bx3_run(g, pick_config(GEMM_PATH_3XBF16, n_products, M, N, K), stream);
 }
 
+int gemm_splitk_default_splits(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 1;
+  return bx3_splitk_default(M, N, K);
+}
+
+size_t gemm_splitk_workspace_bytes(int64_t M, int64_t N, int64_t K, int splits) {
+  if (M < 0 || N < 0 || K < 0 || splits < 0 || splits > 64) return 0;
+  if (splits == 0) splits = gemm_splitk_default_splits(M, N, K);
+  return bx3_splitk_ws_bytes(M, N, splits);
+}
+
+gemm_status gemm_f32_3xbf16_splitk(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                                   int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                                   int64_t ldc, int n_products, int splits, void *workspace,
+                                   size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_f32_3xbf16_splitk";
+  Checked ck;
+  gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st) return st;
+  if (n_products != 3 && n_products != 6) return bad_arg(12, fn, "(n_products) must be 3 or 6");
+  if (splits < 0 || splits > 64) return bad_arg(13, fn, "(splits) must be in [0, 64]");
+  if (ck.noop) return GEMM_STATUS_OK;
+  if (ck.scale_only) return scale_c(M, N, beta, C, ldc, stream);
+  if (splits == 0) splits = bx3_splitk_default(M, N, K);
+  const size_t need = bx3_splitk_ws_bytes(M, N, splits);
+  if (need > 0) {
+    if (!workspace || ((uintptr_t)workspace & 255)) return bad_arg(14, fn, "(workspace) NULL or not 256-byte aligned");
+    if (ws_bytes < need) return bad_arg(15, fn, "(ws_bytes) below gemm_splitk_workspace_bytes");
+  }
+  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc};
+  return bx3_run_splitk(g, n_products, splits, workspace, stream);
+}
+
 gemm_status split_bf16x3(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
                          hipStream_t stream) {
   clear_error();

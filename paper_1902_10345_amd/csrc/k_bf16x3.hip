@@ -1,4 +1,6 @@
 // k_bf16x3.hip -- FP32-accurate split-precision GEMM on bf16 MFMA (gfx950).
+#include <algorithm>
+
 #include "bf16x3.hpp"
 
 namespace mm {
@@ -44,6 +46,106 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   return check_launch("gemm_bx3_kernel");
 }
 
+// ---- split-K ----------------------------------------------------------------
+// Workgroup (chunk c, output tile) multiplies K range [c*chunk, min(K, (c+1)*chunk))
+// of its tile (alpha 1, beta 0) into partial plane c of P (M x N, ld N).
+// Chunks are whole slabs, so the slab grid of every chunk ends on its own
+// boundary and only a chunk's first slab can be partial.
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW, 1) void gemm_bx3_splitk_kernel(
+    int M, int N, int K, int chunk, const float *__restrict__ A, int64_t lda,
+    const float *__restrict__ B, int64_t ldb, float *__restrict__ P, int tiles_m, int tiles_n) {
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[G::LDS_BYTES / 2];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles = tiles_m * tiles_n;
+  const int c = wg / tiles;
+  int tm, tn;
+  tile_coords(wg - c * tiles, tiles_m, tiles_n, 8, tm, tn);
+  const int k0 = c * chunk;
+  const int kc = (K - k0 < chunk ? K - k0 : chunk);
+  tile<BM, BN, BK, WM, WN, NP, NW, VEC, false>(M, N, kc, 1.0f, A + k0, lda, B + (int64_t)k0 * ldb,
+                                               ldb, 0.0f, P + (int64_t)c * M * N, N, tm * BM,
+                                               tn * BN, lds);
+}
+
+// The write-conflict resolution of the chunks: C = alpha * (P_0 + P_1 + ...)
+// + beta * C, summed in chunk order (deterministic), the same epilogue
+// arithmetic as the single-pass kernel.  VEC: N, ldc multiples of 4 and C
+// 16-byte aligned.
+template <bool VEC, bool BETA>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(int M, int N, int S,
+                                                            const float *__restrict__ P,
+                                                            float alpha, float beta,
+                                                            float *__restrict__ C, int64_t ldc) {
+  const int64_t plane = (int64_t)M * N;
+  if (VEC) {
+    const int64_t n4 = plane / 4;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += (int64_t)gridDim.x * 256) {
+      float4 acc = reinterpret_cast<const float4 *>(P)[q];
+      for (int c = 1; c < S; ++c) {
+        const float4 v = reinterpret_cast<const float4 *>(P + c * plane)[q];
+        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+      }
+      const int64_t e = 4 * q;
+      const int64_t i = e / N, j = e - i * N;
+      float4 *cp = reinterpret_cast<float4 *>(C + i * ldc + j);
+      float4 out = make_float4(alpha * acc.x, alpha * acc.y, alpha * acc.z, alpha * acc.w);
+      if (BETA) {
+        const float4 c0 = *cp;
+        out = make_float4(fmaf(beta, c0.x, out.x), fmaf(beta, c0.y, out.y),
+                          fmaf(beta, c0.z, out.z), fmaf(beta, c0.w, out.w));
+      }
+      *cp = out;
+    }
+  } else {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < plane; e += (int64_t)gridDim.x * 256) {
+      float acc = P[e];
+      for (int c = 1; c < S; ++c) acc += P[c * plane + e];
+      const int64_t i = e / N, j = e - i * N;
+      float *cp = C + i * ldc + j;
+      const float v = alpha * acc;
+      *cp = BETA ? fmaf(beta, *cp, v) : v;
+    }
+  }
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
+gemm_status launch_splitk(const GemmArgs &g, int S, float *P, hipStream_t s) {
+  const int tiles_m = (int)((g.M + BM - 1) / BM);
+  const int tiles_n = (int)((g.N + BN - 1) / BN);
+  const int64_t nwg = (int64_t)tiles_m * tiles_n * S;
+  if (nwg > 0x7fffffff) { set_error("gemm_f32_3xbf16_splitk: too many workgroups"); return GEMM_STATUS_UNSUPPORTED; }
+  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 ||
+      ((int64_t)BK * g.ldb + g.N) * 4 >= ((int64_t)1 << 31)) {
+    set_error("gemm_f32_3xbf16_splitk: lda or ldb too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  const int chunk = (int)(((g.K + S - 1) / S + BK - 1) / BK * BK);
+  S = (int)((g.K + chunk - 1) / chunk);  // chunks that hold work (<= requested)
+  const int64_t nwg_used = (int64_t)tiles_m * tiles_n * S;
+  const bool vec = g.lda % 4 == 0 && g.K % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL((gemm_bx3_splitk_kernel<BM, BN, BK, WM, WN, NP, NW, true>), dim3((unsigned)nwg_used),
+                       dim3(64 * NW), 0, s, (int)g.M, (int)g.N, (int)g.K, chunk, g.A, g.lda, g.B,
+                       g.ldb, P, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_bx3_splitk_kernel<BM, BN, BK, WM, WN, NP, NW, false>), dim3((unsigned)nwg_used),
+                       dim3(64 * NW), 0, s, (int)g.M, (int)g.N, (int)g.K, chunk, g.A, g.lda, g.B,
+                       g.ldb, P, tiles_m, tiles_n);
+  if (gemm_status st = check_launch("gemm_bx3_splitk_kernel")) return st;
+  const bool rvec = g.N % 4 == 0 && g.ldc % 4 == 0 && ((uintptr_t)g.C & 15) == 0;
+  const int64_t items = rvec ? g.M * g.N / 4 : g.M * g.N;
+  const unsigned grid = (unsigned)std::min<int64_t>((items + 255) / 256, 4096);
+#define MM_RED(V, BT)                                                                              \
+  hipLaunchKernelGGL((splitk_reduce_kernel<V, BT>), dim3(grid), dim3(256), 0, s, (int)g.M,        \
+                     (int)g.N, S, P, g.alpha, g.beta, g.C, g.ldc)
+  if (rvec) { if (g.beta != 0.0f) MM_RED(true, true); else MM_RED(true, false); }
+  else      { if (g.beta != 0.0f) MM_RED(false, true); else MM_RED(false, false); }
+#undef MM_RED
+  return check_launch("splitk_reduce_kernel");
+}
+
 // Split kernel used to verify the staging split bit for bit.
 __global__ __launch_bounds__(256) void split_kernel(int64_t n, const float *__restrict__ x,
                                                     unsigned short *__restrict__ p0,
@@ -59,6 +161,8 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, const float *__re
 }
 
 }  // namespace bx3
+
+constexpr int kSplitKMax = 64;
 
 // Tile configurations of the split-precision path.  np = planes per operand
 // (2 -> 3 products, 3 -> 6 products).
@@ -108,6 +212,28 @@ gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 8: return bx3::launch<128, 128, 16, 64, 64, 2, 4>(g, s);
     default: set_error("gemm_f32_3xbf16: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
+}
+
+// Split-K uses the 128 x 128 tiles (16-deep slabs for three products,
+// 32-deep for six); a chunk is at least 256 deep.
+int bx3_splitk_default(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+  int64_t s = (2 * (int64_t)num_cus() + tiles - 1) / tiles;
+  const int64_t by_k = K / 256;
+  if (s > by_k) s = by_k;
+  if (s > kSplitKMax) s = kSplitKMax;
+  return (int)(s < 1 ? 1 : s);
+}
+
+size_t bx3_splitk_ws_bytes(int64_t M, int64_t N, int splits) {
+  return splits <= 1 ? 0 : (((size_t)splits * (size_t)M * (size_t)N * 4 + 255) / 256) * 256;
+}
+
+gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *ws, hipStream_t s) {
+  float *P = static_cast<float *>(ws);
+  if (splits <= 1) return bx3_run(g, n_products == 6 ? 5 : 8, s);  // same tile, one pass
+  if (n_products == 6) return bx3::launch_splitk<128, 128, 32, 64, 64, 3, 4>(g, splits, P, s);
+  return bx3::launch_splitk<128, 128, 16, 64, 64, 2, 4>(g, splits, P, s);
 }
 
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,

@@ -34,6 +34,9 @@ const TileConfig &bx3_config(int i);
 int bx3_config_products(int i);
 int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products);
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s);
+int bx3_splitk_default(int64_t M, int64_t N, int64_t K);
+size_t bx3_splitk_ws_bytes(int64_t M, int64_t N, int splits);
+gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *ws, hipStream_t s);
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
                       hipStream_t s);
 

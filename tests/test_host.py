@@ -166,3 +166,29 @@ def test_uniform_is_seeded_and_in_range():
     assert a.min() >= -1.0 and a.max() < 1.0
     p = si.uniform((10, 7), 3, ld=9, pad_value=np.nan)
     assert p.shape == (10, 7) and p.strides[0] == 9 * 4
+
+
+def test_splitk_argument_codes_and_sizes():
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    args = (512, 512, 4096, 1.0, F, 4096, F, 512, 0.0, F, 512)
+    nb = mm.gemm_splitk_workspace_bytes(512, 512, 4096, 4)
+    assert nb == 4 * 512 * 512 * 4
+    assert lib.gemm_f32_3xbf16_splitk(*args, 5, 4, 256, nb, None) == -12
+    assert lib.gemm_f32_3xbf16_splitk(*args, 3, 65, 256, nb, None) == -13
+    assert lib.gemm_f32_3xbf16_splitk(*args, 3, -1, 256, nb, None) == -13
+    assert lib.gemm_f32_3xbf16_splitk(*args, 3, 4, None, nb, None) == -14
+    assert lib.gemm_f32_3xbf16_splitk(*args, 3, 4, 8, nb, None) == -14
+    assert lib.gemm_f32_3xbf16_splitk(*args, 3, 4, 256, nb - 1, None) == -15
+    assert lib.gemm_f32_3xbf16_splitk(0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 3, 4, None, 0,
+                                      None) == 0
+    # one chunk needs no workspace
+    assert mm.gemm_splitk_workspace_bytes(512, 512, 4096, 1) == 0
+    # the default fills the machine with 128 x 128 tiles, chunks >= 256 deep, at most 64
+    for (M, N, K) in [(512, 4096, 4096), (64, 4096, 4096), (4096, 4096, 4096), (256, 256, 256),
+                      (128, 128, 100000)]:
+        s = mm.gemm_splitk_default_splits(M, N, K)
+        assert 1 <= s <= 64 and (s == 1 or K // s >= 256)
+        assert mm.gemm_splitk_workspace_bytes(M, N, K, 0) == mm.gemm_splitk_workspace_bytes(M, N, K, s)
+    assert mm.gemm_splitk_default_splits(4096, 4096, 4096) == 1
+    assert mm.gemm_splitk_default_splits(64, 4096, 4096) == 16
