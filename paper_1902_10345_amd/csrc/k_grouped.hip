@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64) void clear_counter_kernel(unsigned *counter) {
 }
 
 // Tile prefixes of batches up to this size are searched in LDS.
-constexpr int kLdsStarts = 2048;
+constexpr int kLdsStarts = 3072;
 
 __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict__ descs,
                                                          const int *__restrict__ starts, int count,
@@ -68,7 +68,11 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
     for (int i = threadIdx.x; i <= count; i += 256) s_starts[i] = starts[i];
   if (threadIdx.x == 0) s_tile[0] = (int)atomicAdd(counter, 1u);
   __syncthreads();
-  int t = s_tile[0];
+  // Values read from LDS are per-lane to the compiler; the tile index is
+  // wave-uniform by construction, and saying so keeps everything derived
+  // from it (tile origin, buffer resources) in scalar registers -- a per-lane
+  // buffer resource turns every buffer load into a readfirstlane loop.
+  int t = __builtin_amdgcn_readfirstlane(s_tile[0]);
   for (int it = 1; t < total_tiles; ++it) {
     // Dequeue the next tile now: the atomic's round trip overlaps this tile's
     // work, and its result is only read after the tile.
@@ -91,9 +95,13 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const Desc d = descs[lo];
-    const int local = t - starts_at(in_lds, s_starts, starts, lo);
+    const int local = t - __builtin_amdgcn_readfirstlane(starts_at(in_lds, s_starts, starts, lo));
     const int bm = d.variant == 0 ? 128 : 64, bn = bm;
-    const int m0 = (local / d.tiles_n) * bm, n0 = (local % d.tiles_n) * bn;
+    // tiles of a problem in groups of 8 tile rows, as in the single-GEMM
+    // kernels: consecutive dequeues share A row panels and B column panels
+    int tm, tn;
+    tile_coords(local, (d.M + bm - 1) / bm, d.tiles_n, 8, tm, tn);
+    const int m0 = tm * bm, n0 = tn * bn;
     const int sel = d.variant * 4 + (d.vec ? 2 : 0) + (d.beta != 0.0f ? 1 : 0);
     switch (sel) {
       case 0: run_tile<0, false, false>(d, m0, n0, lds); break;
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
     // tile's last LDS reads from the next tile's first LDS writes.
     if (threadIdx.x == 0) s_tile[it & 1] = (int)next;
     __syncthreads();
-    t = s_tile[it & 1];
+    t = __builtin_amdgcn_readfirstlane(s_tile[it & 1]);
   }
 }
 
