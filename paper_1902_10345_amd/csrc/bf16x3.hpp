@@ -67,15 +67,21 @@ struct Cfg {
   static_assert(WAVES_M * WAVES_N == NW, "wave grid must cover the tile");
   static constexpr int FM = WM / 32;          // 32x32 blocks per wave along M
   static constexpr int FN = WN / 32;
-  static constexpr int CH = BK / 8;           // 16-byte chunks per LDS row
-  static constexpr int KS = BK / 16;          // MFMA k-steps per slab
+  static constexpr int CH = BK / 8;           // 8-element staging items per row
+  // LDS row length in bf16 units: BK bf16 per plane, or BK binary32 values
+  // (twice the bytes) in the FP32 mode (NP == 1)
+  static constexpr int ROW = NP == 1 ? 2 * BK : BK;
+  static constexpr int NPL = NP == 1 ? 2 : NP;  // bf16-plane sizes per operand
+  // MFMA k-steps per slab: 16 k (bf16 planes) or 8 k (FP32 mode: two 4-k
+  // chunks per lane pair, each feeding four 32x32x2 MFMAs)
+  static constexpr int KS = NP == 1 ? BK / 8 : BK / 16;
   static constexpr int A_ITEMS = BM * CH / NT;    // (row, chunk) items per lane
   static constexpr int B_ITEMS = BN * CH / NT;    // (col, chunk) items per lane
   static_assert(A_ITEMS * NT == BM * CH && B_ITEMS * NT == BN * CH, "even split");
   static_assert(BN % 64 == 0 || NT % BN == 0, "B chunk index must be wave-uniform");
   static constexpr int PLANE_A = BM * BK;     // bf16 elements per A plane
   static constexpr int PLANE_B = BN * BK;
-  static constexpr int STAGE = NP * (PLANE_A + PLANE_B);  // bf16 per stage
+  static constexpr int STAGE = NPL * (PLANE_A + PLANE_B);  // bf16 units per stage
   static constexpr int LDS_BYTES = 2 * STAGE * 2;
   // Register sets for slabs in flight: with BK >= 32 one slab's MFMA work
   // (2 k-steps) already covers the load latency, so one set is kept and the
@@ -216,28 +222,51 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   auto sstore = [&](auto S, int stage) {
     constexpr int set = decltype(S)::value;
     __bf16 *sA = lds + stage * G::STAGE;
-    __bf16 *sB = sA + NP * G::PLANE_A;
+    __bf16 *sB = sA + G::NPL * G::PLANE_A;
+    if constexpr (NP == 1) {  // FP32 mode: the item's 8 values as two 16-byte chunks
 #pragma unroll
-    for (int i = 0; i < G::A_ITEMS; ++i) {
-      const int idx = tid + NT * i;
-      const int r = idx / CH, c = idx % CH;
-      bf16x8 h, m, l;
-      split8(ra[set][i], h, m, l);
-      const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
-      *reinterpret_cast<bf16x8 *>(sA + off) = h;
-      *reinterpret_cast<bf16x8 *>(sA + G::PLANE_A + off) = m;
-      if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sA + 2 * G::PLANE_A + off) = l;
-    }
+      for (int i = 0; i < G::A_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int r = idx / CH, c = idx % CH;
+        const float *x = ra[set][i];
+        *reinterpret_cast<f32x4 *>(sA + r * G::ROW + (((2 * c) ^ swz<G::ROW>(r)) << 3)) =
+            f32x4{x[0], x[1], x[2], x[3]};
+        *reinterpret_cast<f32x4 *>(sA + r * G::ROW + (((2 * c + 1) ^ swz<G::ROW>(r)) << 3)) =
+            f32x4{x[4], x[5], x[6], x[7]};
+      }
 #pragma unroll
-    for (int i = 0; i < G::B_ITEMS; ++i) {
-      const int idx = tid + NT * i;
-      const int n = idx % BN, c = idx / BN;
-      bf16x8 h, m, l;
-      split8(rb[set][i], h, m, l);
-      const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
-      *reinterpret_cast<bf16x8 *>(sB + off) = h;
-      *reinterpret_cast<bf16x8 *>(sB + G::PLANE_B + off) = m;
-      if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sB + 2 * G::PLANE_B + off) = l;
+      for (int i = 0; i < G::B_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int n = idx % BN, c = idx / BN;
+        const float *x = rb[set][i];
+        *reinterpret_cast<f32x4 *>(sB + n * G::ROW + (((2 * c) ^ swz<G::ROW>(n)) << 3)) =
+            f32x4{x[0], x[1], x[2], x[3]};
+        *reinterpret_cast<f32x4 *>(sB + n * G::ROW + (((2 * c + 1) ^ swz<G::ROW>(n)) << 3)) =
+            f32x4{x[4], x[5], x[6], x[7]};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < G::A_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int r = idx / CH, c = idx % CH;
+        bf16x8 h, m, l;
+        split8(ra[set][i], h, m, l);
+        const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
+        *reinterpret_cast<bf16x8 *>(sA + off) = h;
+        *reinterpret_cast<bf16x8 *>(sA + G::PLANE_A + off) = m;
+        if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sA + 2 * G::PLANE_A + off) = l;
+      }
+#pragma unroll
+      for (int i = 0; i < G::B_ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int n = idx % BN, c = idx / BN;
+        bf16x8 h, m, l;
+        split8(rb[set][i], h, m, l);
+        const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
+        *reinterpret_cast<bf16x8 *>(sB + off) = h;
+        *reinterpret_cast<bf16x8 *>(sB + G::PLANE_B + off) = m;
+        if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sB + 2 * G::PLANE_B + off) = l;
+      }
     }
   };
 
@@ -255,56 +284,83 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
 
   // Fragments of one 16-deep k-step: the lane's 8 consecutive k of its A row
   // (per block i and plane p) and of its B column (per block j and plane p).
+  using FragT = std::conditional_t<NP == 1, f32x4, bf16x8>;
   struct Frags {
-    bf16x8 a[NP][G::FM], b[NP][G::FN];
+    FragT a[NP][G::FM], b[NP][G::FN];
   };
   // Reads in the order the products consume them (b0 and a1 first).
   auto frag_read = [&](Frags &f, int stage, int ks) {
     const __bf16 *sA = lds + stage * G::STAGE;
-    const __bf16 *sB = sA + NP * G::PLANE_A;
+    const __bf16 *sB = sA + G::NPL * G::PLANE_A;
     const int c = ks * 2 + lgrp;  // logical 16-byte chunk of this lane
-    auto rd_b = [&](int p) {
+    if constexpr (NP == 1) {  // FP32 mode: 4 consecutive k per lane and block
 #pragma unroll
       for (int j = 0; j < G::FN; ++j) {
         const int n = wn0 + j * 32 + lrow;
-        f.b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + n * BK +
-                                                      ((c ^ swz<BK>(n)) << 3));
+        f.b[0][j] = *reinterpret_cast<const f32x4 *>(sB + n * G::ROW + ((c ^ swz<G::ROW>(n)) << 3));
       }
-    };
-    auto rd_a = [&](int p) {
 #pragma unroll
       for (int i = 0; i < G::FM; ++i) {
         const int r = wm0 + i * 32 + lrow;
-        f.a[p][i] = *reinterpret_cast<const bf16x8 *>(sA + p * G::PLANE_A + r * BK +
-                                                      ((c ^ swz<BK>(r)) << 3));
+        f.a[0][i] = *reinterpret_cast<const f32x4 *>(sA + r * G::ROW + ((c ^ swz<G::ROW>(r)) << 3));
       }
-    };
-    rd_b(0);
-    if constexpr (NP == 3) rd_a(2);
-    rd_a(1);
-    rd_b(1);
-    if constexpr (NP == 3) rd_b(2);
-    rd_a(0);
+    } else {
+      auto rd_b = [&](int p) {
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j) {
+          const int n = wn0 + j * 32 + lrow;
+          f.b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + n * BK +
+                                                        ((c ^ swz<BK>(n)) << 3));
+        }
+      };
+      auto rd_a = [&](int p) {
+#pragma unroll
+        for (int i = 0; i < G::FM; ++i) {
+          const int r = wm0 + i * 32 + lrow;
+          f.a[p][i] = *reinterpret_cast<const bf16x8 *>(sA + p * G::PLANE_A + r * BK +
+                                                        ((c ^ swz<BK>(r)) << 3));
+        }
+      };
+      rd_b(0);
+      if constexpr (NP == 3) rd_a(2);
+      rd_a(1);
+      rd_b(1);
+      if constexpr (NP == 3) rd_b(2);
+      rd_a(0);
+    }
   };
   // Small products first, the leading product last; consecutive MFMAs go to
   // different accumulator blocks.
   auto frag_mfma = [&](const Frags &f) {
-    auto prod = [&](int pa, int pb) {
+    if constexpr (NP == 1) {
+      // MFMA q sums k = 4c + q of the lower half-wave's chunk and of the
+      // upper half-wave's chunk: every k of the two chunks exactly once
 #pragma unroll
-      for (int i = 0; i < G::FM; ++i)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[pa][i], f.b[pb][j], acc[i][j],
-                                                              0, 0, 0);
-    };
-    if constexpr (NP == 3) {
-      prod(2, 0);
-      prod(1, 1);
-      prod(0, 2);
+        for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < G::FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[0][i][q], f.b[0][j][q], acc[i][j],
+                                                             0, 0, 0);
+    } else {
+      auto prod = [&](int pa, int pb) {
+#pragma unroll
+        for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < G::FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[pa][i], f.b[pb][j], acc[i][j],
+                                                                0, 0, 0);
+      };
+      if constexpr (NP == 3) {
+        prod(2, 0);
+        prod(1, 1);
+        prod(0, 2);
+      }
+      prod(1, 0);
+      prod(0, 1);
+      prod(0, 0);
     }
-    prod(1, 0);
-    prod(0, 1);
-    prod(0, 0);
   };
   // All MFMAs of one LDS stage.  With one k-step per stage every fragment
   // read is issued before the first MFMA (a scheduling barrier stops the
@@ -364,6 +420,24 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       sstore(S0{}, 1);
       __syncthreads();
       gload(S0{}, Fast{}, kslab(t + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_stage(1);
+      sstore(S0{}, 0);
+      __syncthreads();
+    }
+  } else if constexpr (NP == 1) {
+    // FP32 mode, two register sets: 64 MFMAs per wave and slab leave the
+    // loads and stores plenty of room; the compiler schedules them.
+    if (KT > 1) gload(S1{}, Fast{}, kslab(1));
+    else gload(S1{}, Masked{}, kbase);
+    __syncthreads();
+    for (; t + 2 <= KT; t += 2) {
+      gload(S0{}, Fast{}, kslab(t + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_stage(0);
+      sstore(S1{}, 1);
+      __syncthreads();
+      gload(S1{}, Fast{}, kslab(t + 3));
       __builtin_amdgcn_sched_barrier(0);
       mfma_stage(1);
       sstore(S0{}, 0);

@@ -20,6 +20,46 @@ __global__ __launch_bounds__(64 * NW, 1) void gemm_bx3_kernel(
                                          tm * BM, tn * BN, lds);
 }
 
+// The plain binary32 product on the FP32 matrix cores (v_mfma_f32_32x32x2f32):
+// the same tile body in its FP32 mode (no split; binary32 in LDS).
+template <int BM, int BN, int BK, int WM, int WN, int NW, bool VEC, bool BETA>
+__global__ __launch_bounds__(64 * NW, 1) void gemm_f32mfma_kernel(
+    int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda,
+    const float *__restrict__ B, int64_t ldb, float beta, float *__restrict__ C, int64_t ldc,
+    int tiles_m, int tiles_n) {
+  using G = Cfg<BM, BN, BK, WM, WN, 1, NW>;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[G::LDS_BYTES / 2];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
+  tile<BM, BN, BK, WM, WN, 1, NW, VEC, BETA>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                         tm * BM, tn * BN, lds);
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int NW>
+gemm_status launch_f32mfma(const GemmArgs &g, hipStream_t s) {
+  const int tiles_m = (int)((g.M + BM - 1) / BM);
+  const int tiles_n = (int)((g.N + BN - 1) / BN);
+  const int64_t nwg = (int64_t)tiles_m * tiles_n;
+  if (nwg > 0x7fffffff) { set_error("gemm_f32: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
+  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 ||
+      ((int64_t)BK * g.ldb + g.N) * 4 >= ((int64_t)1 << 31)) {
+    set_error("gemm_f32: lda or ldb too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  const bool vec = g.lda % 4 == 0 && g.K % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
+  const bool beta = g.beta != 0.0f;
+  dim3 grid((unsigned)nwg), block(64 * NW);
+#define MM_LAUNCH(V, BT)                                                                     \
+  hipLaunchKernelGGL((gemm_f32mfma_kernel<BM, BN, BK, WM, WN, NW, V, BT>), grid, block, 0, s, \
+                     (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta,  \
+                     g.C, g.ldc, tiles_m, tiles_n)
+  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
+  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
+#undef MM_LAUNCH
+  return check_launch("gemm_f32mfma_kernel");
+}
+
 template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
 gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const int tiles_m = (int)((g.M + BM - 1) / BM);
@@ -234,6 +274,11 @@ gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *
   if (splits <= 1) return bx3_run(g, n_products == 6 ? 5 : 8, s);  // same tile, one pass
   if (n_products == 6) return bx3::launch_splitk<128, 128, 32, 64, 64, 3, 4>(g, splits, P, s);
   return bx3::launch_splitk<128, 128, 16, 64, 64, 2, 4>(g, splits, P, s);
+}
+
+gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
+  if (which == 0) return bx3::launch_f32mfma<256, 256, 16, 128, 64, 8>(g, s);
+  return bx3::launch_f32mfma<128, 128, 16, 64, 64, 4>(g, s);
 }
 
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,

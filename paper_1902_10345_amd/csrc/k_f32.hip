@@ -252,6 +252,10 @@ static const TileConfig kF32Configs[] = {
     {128, 64, 32, "f32_128x64x32_r8x4"},
     {128, 128, 32, "f32_128x128x32_r8x8_u2"},
     {128, 64, 32, "f32_128x64x32_r8x4_u2"},
+    // binary32 products on the FP32 matrix cores (same arithmetic; the tile
+    // body of the split-precision path in its FP32 mode)
+    {256, 256, 16, "f32mfma_256x256x16_8w128x64"},
+    {128, 128, 16, "f32mfma_128x128x16_4w64x64"},
 };
 
 int f32_num_configs() { return (int)(sizeof(kF32Configs) / sizeof(kF32Configs[0])); }
@@ -259,13 +263,13 @@ const TileConfig &f32_config(int i) { return kF32Configs[i]; }
 
 int f32_default_config(int64_t M, int64_t N, int64_t K) {
   (void)K;
-  // measured: a tile shape wins while it gives every CU at least two tiles
+  // measured: the FP32 matrix-core tiles win while they fill every CU (256 x
+  // 256: 140 TFLOP/s at 4096^3 against 90 on the vector ALU); below that the
+  // 64 x 64 vector-ALU tile, which fills the machine with more workgroups
   const int64_t cus = num_cus();
-  const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-  if (big >= 2 * cus) return 3;  // 128 x 128, k loop unrolled by 2
-  const int64_t mid = ((M + 127) / 128) * ((N + 63) / 64);
-  if (mid >= 2 * cus) return 4;  // 128 x 64, unrolled by 2
-  return 1;                       // 64 x 64
+  if (((M + 255) / 256) * ((N + 255) / 256) >= cus) return 5;
+  if (((M + 127) / 128) * ((N + 127) / 128) >= cus) return 6;
+  return 1;
 }
 
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
@@ -275,6 +279,8 @@ gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 2: return f32::launch<128, 64, 32, 8, 4, 1>(g, s);
     case 3: return f32::launch<128, 128, 32, 8, 8, 2>(g, s);
     case 4: return f32::launch<128, 64, 32, 8, 4, 2>(g, s);
+    case 5: return f32mfma_run(g, 0, s);
+    case 6: return f32mfma_run(g, 1, s);
     default: set_error("gemm_f32: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

@@ -35,6 +35,8 @@ int bx3_config_products(int i);
 int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products);
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s);
 int bx3_splitk_default(int64_t M, int64_t N, int64_t K);
+// FP32 matrix-core tiles of the plain path: 0 = 256 x 256 (8 waves), 1 = 128 x 128 (4 waves)
+gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s);
 size_t bx3_splitk_ws_bytes(int64_t M, int64_t N, int splits);
 gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *ws, hipStream_t s);
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,

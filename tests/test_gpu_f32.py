@@ -66,6 +66,22 @@ def test_every_config():
         _check(A, B, C0, C, 1.5, 0.5)
 
 
+def test_every_config_integer_inputs_are_exact():
+    """Vector-ALU and FP32 matrix-core tiles alike: integer inputs in [-8, 8]
+    keep every partial sum an integer below 2^24, so each configuration is
+    exact whatever its summation order."""
+    import torch
+    import paper_1902_10345_amd as mm
+    M, N, K = 300, 260, 1000
+    A, B, C0 = si.integers((M, K), 44), si.integers((K, N), 45), si.integers((M, N), 46)
+    ref = oracle.gemm(A, B, alpha=2.0, beta=-1.0, C0=C0)
+    for cfg in range(mm.gemm_num_configs(mm.PATH_F32)):
+        dA, dB, dC = (torch.from_numpy(x).cuda() for x in (A, B, C0))
+        mm.gemm_run_config(mm.PATH_F32, cfg, M, N, K, 2.0, dA, K, dB, N, -1.0, dC, N)
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy().astype(np.float64), ref), mm.gemm_config_name(0, cfg)
+
+
 def test_padded_leading_dimensions_and_untouched_padding():
     import paper_1902_10345_amd as mm
     M, N, K = 133, 97, 71
