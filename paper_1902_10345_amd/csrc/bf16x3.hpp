@@ -54,7 +54,10 @@ __device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
 // XOR swizzle of the 16-byte chunk index of an LDS row holding BK bf16.
 template <int BK>
 __device__ __forceinline__ int swz(int r) {
-  if constexpr (BK == 32) return ((r >> 1) ^ (r >> 3)) & 3;
+  // 64-byte rows: measured on gfx950 with SQ_LDS_BANK_CONFLICT, this form is
+  // conflict-free for the fragment reads, the row-major A stores and the
+  // transposed B stores; ((r >> 1) ^ (r >> 3)) & 3 conflicts on the reads
+  if constexpr (BK == 32) return (r ^ (r >> 2)) & 3;
   else if constexpr (BK == 16) return ((r >> 2) ^ (r >> 3)) & 1;
   else return 0;
 }

@@ -231,7 +231,7 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   const int64_t cus = num_cus();
   const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
   if (n_products == 6) return big >= cus ? 4 : 5;
-  if (big >= cus) return 0;
+  if (big >= cus) return 3;  // 256 x 256 x 32: 1-2 % ahead of the 16-deep slabs, every run
   // measured: once 256 x 256 tiles leave CUs idle, 128 x 128 x 16 tiles win
   // while they still fill every CU, below that 64 x 64 tiles
   const int64_t small = ((M + 127) / 128) * ((N + 127) / 128);
