@@ -58,7 +58,7 @@ constexpr int kLdsStarts = 3072;
 
 __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict__ descs,
                                                          const int *__restrict__ starts, int count,
-                                                         int total_tiles,
+                                                         int total_tiles, int static_tiles,
                                                          unsigned *__restrict__ counter) {
   __shared__ __attribute__((aligned(16))) __bf16 lds[kLdsBytes / 2];
   __shared__ int s_starts[kLdsStarts];
@@ -66,7 +66,16 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
   const bool in_lds = count < kLdsStarts;
   if (in_lds)
     for (int i = threadIdx.x; i <= count; i += 256) s_starts[i] = starts[i];
-  if (threadIdx.x == 0) s_tile[0] = (int)atomicAdd(counter, 1u);
+  // Tiles [0, static_tiles) are dealt round-robin (tile t to workgroup t mod
+  // G): the list is sorted longest first, so each round hands every
+  // workgroup a tile of similar cost and needs no atomics.  The remaining
+  // tiles are dequeued from the counter (first come, first served), which
+  // evens out the tail; a whole grid's worth of simultaneous same-address
+  // atomics would otherwise serialise at the start of every launch.
+  const int G = gridDim.x;
+  if (threadIdx.x == 0)
+    s_tile[0] = (int)blockIdx.x < static_tiles ? (int)blockIdx.x
+                                               : static_tiles + (int)atomicAdd(counter, 1u);
   __syncthreads();
   // Values read from LDS are per-lane to the compiler; the tile index is
   // wave-uniform by construction, and saying so keeps everything derived
@@ -77,7 +86,10 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
     // Dequeue the next tile now: the atomic's round trip overlaps this tile's
     // work, and its result is only read after the tile.
     unsigned next = 0u;
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+    if (threadIdx.x == 0)
+      next = (t + G < static_tiles || static_tiles >= total_tiles)
+                 ? (unsigned)(t + G)
+                 : (unsigned)static_tiles + atomicAdd(counter, 1u);
     // owning problem: the last p with starts[p] <= t
     int lo = 0, hi = count - 1;
     if (in_lds) {
@@ -190,8 +202,12 @@ gemm_status grouped_enqueue(void *ws, int count, int total, int grid, hipStream_
   hipLaunchKernelGGL(grp::clear_counter_kernel, dim3(1), dim3(64), 0, s, counter);
   if (gemm_status st = check_launch("clear_counter_kernel")) return st;
   if (total == 0) return GEMM_STATUS_OK;
+  // all but the last two rounds are dealt statically, and at least the first
+  // round (a batch of at most one round needs no atomics at all)
+  const int rounds = total / grid;
+  const int static_tiles = rounds > 2 ? (rounds - 2) * grid : std::min(total, grid);
   hipLaunchKernelGGL(grp::grouped_kernel, dim3(grid), dim3(256), 0, s, descs, starts, count, total,
-                     counter);
+                     static_tiles, counter);
   return check_launch("grouped_kernel");
 }
 
