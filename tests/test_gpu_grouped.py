@@ -143,3 +143,34 @@ def test_invalid_member_is_rejected_before_enqueue():
     with pytest.raises(mm.GemmError) as e:
         mm.grouped_gemm(arr, 3, mm.PATH_3XBF16, None, ws, ws.numel())
     assert e.value.status == -1 and "problems[1]" in e.value.message
+
+
+def test_large_batch_prefix_search_in_global_memory_and_mixed_schedule():
+    """More problems than the kernel's LDS copy of the tile prefix holds
+    (3500 > 3072): the owning problem is found by binary search in global
+    memory.  With several rounds of tiles the first rounds are dealt
+    round-robin and the rest dequeued from the counter; every tile must be
+    computed exactly once."""
+    import torch
+    import paper_1902_10345_amd as mm
+    count = 3500
+    g = np.random.default_rng(77)
+    sizes = [(int(g.integers(1, 70)), int(g.integers(1, 70)), int(g.integers(1, 90))) for _ in range(count)]
+    sizes[17] = (300, 260, 200)   # a few multi-tile members among the small ones
+    sizes[2000] = (130, 700, 64)
+    probs = []
+    for t, (M, N, K) in enumerate(sizes):
+        probs.append([M, N, K, si.integers((M, K), 10 * t), si.integers((K, N), 10 * t + 1),
+                      si.integers((M, N), 10 * t + 2)])
+    dev, arr = _to_device(probs, 2.0, -1.0)
+    ws_bytes = mm.grouped_gemm_workspace_bytes(count)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    for rep in range(2):   # the counter must be re-armed by each launch
+        for (M, N, K, dA, lda, dB, ldb, dC, ldc, a, b), (_, _, _, _, _, C0) in zip(dev, probs):
+            dC.copy_(torch.from_numpy(C0))
+        mm.grouped_gemm(arr, count, mm.PATH_3XBF16, None, ws, ws_bytes)
+        torch.cuda.synchronize()
+        for (M, N, K, A, B, C0), d in zip(probs, dev):
+            got = d[7].cpu().numpy().astype(np.float64)
+            # integer inputs in [-8, 8]: exact on both split planes
+            assert np.array_equal(got, oracle.gemm(A, B, alpha=2.0, beta=-1.0, C0=C0)), (M, N, K, rep)
