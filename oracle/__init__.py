@@ -19,6 +19,10 @@ What it computes (Ben-Nun et al., SC'19):
   * ``e4m3_*`` / ``fp8_*`` -- OCP OFP8 E4M3 encode/decode (RNE, saturating),
                           per-row / per-column scales, and the dequantised-input
                           product (not in the paper).
+  * ``gemm_op``        -- the same product over operands held in a storage
+                          order with transpose flags, as the BLAS-style
+                          external-code call of Sec. 2.1 passes them:
+                          alpha*op(A)@op(B) + beta*C, op(X) = X or X^T.
   * ``norms``          -- relative Frobenius error and componentwise maximum.
 """
 from __future__ import annotations
@@ -137,6 +141,35 @@ def gemm_abs(A, B, alpha=1.0, beta=0.0, C0=None, nthreads=0):
     _load().orc_gemm(M, N, K, float(alpha), _p(A), _ld(A, K), _p(B), _ld(B, N),
                      float(beta), _p(c0), ldc0, _p(out), 1, int(nthreads))
     return out
+
+
+ROW_MAJOR, COL_MAJOR = 101, 102
+NO_TRANS, TRANS = 111, 112
+
+
+def stored_matrix(buf, order, rows, cols, ld):
+    """The rows x cols binary32 matrix held in the flat buffer `buf`: element
+    (r, c) sits at r*ld + c in row-major order and at c*ld + r in
+    column-major order."""
+    buf = np.asarray(buf, dtype=np.float32).reshape(-1)
+    r = np.arange(rows, dtype=np.int64)[:, None]
+    c = np.arange(cols, dtype=np.int64)[None, :]
+    idx = r * ld + c if order == ROW_MAJOR else c * ld + r
+    return np.ascontiguousarray(buf[idx], dtype=np.float32)
+
+
+def gemm_op(order, trans_a, trans_b, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+            nthreads=0):
+    """alpha*op(A)@op(B) + beta*C in binary64 (M x N), reading each operand
+    from its flat storage buffer.  op(A) is M x K: A itself (stored M x K) or,
+    with trans_a == TRANS, the transpose of A stored K x M; op(B) likewise
+    (B stored K x N, or N x K).  C (stored M x N) is unread when beta == 0."""
+    a = stored_matrix(A, order, K if trans_a == TRANS else M, M if trans_a == TRANS else K, lda)
+    b = stored_matrix(B, order, N if trans_b == TRANS else K, K if trans_b == TRANS else N, ldb)
+    op_a = np.ascontiguousarray(a.T) if trans_a == TRANS else a
+    op_b = np.ascontiguousarray(b.T) if trans_b == TRANS else b
+    c0 = stored_matrix(C, order, M, N, ldc) if beta != 0.0 else None
+    return gemm(op_a, op_b, alpha=alpha, beta=beta, C0=c0, nthreads=nthreads)
 
 
 def bf16_rne(x: float) -> float:

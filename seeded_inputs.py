@@ -62,6 +62,32 @@ def with_ld(x: np.ndarray, ld: int | None, pad_value: float = 0.0) -> np.ndarray
     return buf[:, :cols]
 
 
+def storage(x: np.ndarray, order: str, ld: int, pad_value: float = float("nan")) -> np.ndarray:
+    """Flat binary32 buffer holding matrix x in storage order `order` ("C":
+    row-major, rows of ld elements; "F": column-major, columns of ld
+    elements), built from numpy's own C- and Fortran-ordered arrays.  The
+    ld - extent padding elements hold pad_value."""
+    rows, cols = x.shape
+    if order == "C":
+        assert ld >= max(1, cols)
+        buf = np.full((max(rows, 1), ld), pad_value, dtype=np.float32, order="C")
+        buf[:rows, :cols] = x
+        return buf.ravel(order="C")
+    assert order == "F" and ld >= max(1, rows)
+    buf = np.full((ld, max(cols, 1)), pad_value, dtype=np.float32, order="F")
+    buf[:rows, :cols] = x
+    return buf.ravel(order="F")
+
+
+def unstorage(buf: np.ndarray, order: str, rows: int, cols: int, ld: int) -> np.ndarray:
+    """Inverse of storage(): the rows x cols matrix held in a flat buffer."""
+    if order == "C":
+        return np.asarray(buf[:rows * ld]).reshape(rows, ld, order="C")[:, :cols] if rows else \
+            np.zeros((0, cols), np.float32)
+    return np.asarray(buf[:cols * ld]).reshape(ld, cols, order="F")[:rows, :] if cols else \
+        np.zeros((rows, 0), np.float32)
+
+
 def outlier_columns(n_cols: int, frac: float, seed: int) -> np.ndarray:
     """Sorted indices of ceil(frac * n_cols) distinct seeded columns."""
     g = rng(seed)

@@ -363,3 +363,79 @@ def test_norms_componentwise_and_zero():
     assert oracle.norms(C, C.astype(np.float64))[0] == 0.0
     den2 = np.array([[1.0, 0.0], [1.0, 1.0]])
     assert math.isinf(oracle.norms(C, R, den2)[3])
+
+
+# ---- storage order and transposed operands (BLAS-style call, Sec. 2.1) ----
+
+_ORDERS = [(oracle.ROW_MAJOR, "C"), (oracle.COL_MAJOR, "F")]
+
+
+@pytest.mark.parametrize("order,np_order", _ORDERS)
+def test_stored_matrix_reads_numpy_strided_layouts(order, np_order):
+    """The oracle's element index agrees with numpy's own strides: a row-major
+    matrix with row stride ld is the (ld*4, 4)-strided view of its buffer, a
+    column-major one the (4, ld*4)-strided view."""
+    rows, cols = 5, 7
+    x = si.uniform((rows, cols), 3)
+    ld = (cols if np_order == "C" else rows) + 3
+    buf = si.storage(x, np_order, ld)
+    strides = (ld * 4, 4) if np_order == "C" else (4, ld * 4)
+    view = np.lib.stride_tricks.as_strided(buf, shape=(rows, cols), strides=strides)
+    assert np.array_equal(view, x)
+    assert np.array_equal(oracle.stored_matrix(buf, order, rows, cols, ld), x)
+    assert np.array_equal(si.unstorage(buf, np_order, rows, cols, ld), x)
+    # the padding is never part of the matrix
+    assert np.isnan(buf).sum() == buf.size - rows * cols
+
+
+@pytest.mark.parametrize("order,np_order", _ORDERS)
+@pytest.mark.parametrize("ta", [oracle.NO_TRANS, oracle.TRANS])
+@pytest.mark.parametrize("tb", [oracle.NO_TRANS, oracle.TRANS])
+def test_gemm_op_exact_integer_products(order, np_order, ta, tb):
+    """alpha*op(A)op(B) + beta*C against exact Python integers, for operands
+    placed in memory by numpy (C or Fortran order, padded leading
+    dimensions), with M, N, K distinct so that a misread or mis-transposed
+    operand cannot go unnoticed."""
+    M, N, K = 4, 3, 5
+    op_a, op_b, c0 = si.integers((M, K), 1), si.integers((K, N), 2), si.integers((M, N), 3)
+    a_st = op_a.T.copy() if ta == oracle.TRANS else op_a
+    b_st = op_b.T.copy() if tb == oracle.TRANS else op_b
+
+    def ld_of(x):
+        return (x.shape[1] if np_order == "C" else x.shape[0]) + 2
+
+    lda, ldb, ldc = ld_of(a_st), ld_of(b_st), ld_of(c0)
+    got = oracle.gemm_op(order, ta, tb, M, N, K, 2.0, si.storage(a_st, np_order, lda), lda,
+                         si.storage(b_st, np_order, ldb), ldb, -1.0,
+                         si.storage(c0, np_order, ldc), ldc)
+    exact = [[2 * sum(int(op_a[i, k]) * int(op_b[k, j]) for k in range(K)) - int(c0[i, j])
+              for j in range(N)] for i in range(M)]
+    assert np.array_equal(got, np.array(exact, dtype=np.float64))
+
+
+@pytest.mark.parametrize("ta", [oracle.NO_TRANS, oracle.TRANS])
+@pytest.mark.parametrize("tb", [oracle.NO_TRANS, oracle.TRANS])
+def test_column_major_is_the_transposed_row_major_product(ta, tb):
+    """(op(A) op(B))^T = op(B)^T op(A)^T: a column-major product over given
+    buffers equals the transpose of the row-major product over the same
+    buffers with the operands exchanged, M and N exchanged and each operand
+    keeping its flag."""
+    M, N, K = 6, 4, 9
+    bufA = si.uniform((1, 200), 11).reshape(-1)
+    bufB = si.uniform((1, 200), 12).reshape(-1)
+    bufC = si.uniform((1, 200), 13).reshape(-1)
+    lda = (K if ta == oracle.TRANS else M) + 1
+    ldb = (N if tb == oracle.TRANS else K) + 1
+    ldc = M + 1
+    col = oracle.gemm_op(oracle.COL_MAJOR, ta, tb, M, N, K, 1.5, bufA, lda, bufB, ldb, 0.5, bufC, ldc)
+    row = oracle.gemm_op(oracle.ROW_MAJOR, tb, ta, N, M, K, 1.5, bufB, ldb, bufA, lda, 0.5, bufC, ldc)
+    assert np.array_equal(col, row.T)
+
+
+def test_gemm_op_beta_zero_never_reads_c():
+    M, N, K = 3, 2, 4
+    a, b = si.integers((M, K), 5), si.integers((K, N), 6)
+    bufC = np.full(M * N, np.nan, dtype=np.float32)
+    got = oracle.gemm_op(oracle.ROW_MAJOR, oracle.NO_TRANS, oracle.NO_TRANS, M, N, K, 1.0,
+                         a.reshape(-1), K, b.reshape(-1), N, 0.0, bufC, N)
+    assert np.array_equal(got, a.astype(np.float64) @ b.astype(np.float64))
