@@ -344,6 +344,17 @@ def main():
             flops, PEAK_FP32_VALU, "fp32_valu_peak")
         one("3xbf16_n6_4096^3", lambda: mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, Cf, N, 6),
             flops, PEAK_BF16_MFMA, "bf16_peak")
+        # transposed operands (the square buffers read as A^T stored K x M, B^T stored N x K)
+        for tag, ta, tb in (("TN", mm.TRANS, mm.NO_TRANS), ("NT", mm.NO_TRANS, mm.TRANS),
+                            ("TT", mm.TRANS, mm.TRANS)):
+            one("3xbf16_n3_4096^3_" + tag,
+                lambda ta=ta, tb=tb: mm.gemm_ex(mm.ROW_MAJOR, ta, tb, M, N, K, 1.5, A, M, B, K, 0.5,
+                                                Cf, N, mm.PATH_3XBF16, 3),
+                flops, PEAK_BF16_MFMA, "bf16_peak")
+        one("f32_4096^3_TN",
+            lambda: mm.gemm_ex(mm.ROW_MAJOR, mm.TRANS, mm.NO_TRANS, M, N, K, 1.5, A, M, B, N, 0.5,
+                               Cf, N, mm.PATH_F32, 3),
+            flops, PEAK_FP32_VALU, "fp32_peak")
         nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         An = torch.randn(M, K, device="cuda")

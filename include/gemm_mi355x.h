@@ -12,7 +12,8 @@
  * Conventions shared by every entry point
  *   - Layout: row-major.  A is MxK with row stride lda >= max(1,K); B is KxN
  *     with row stride ldb >= max(1,N); C is MxN with row stride ldc >= max(1,N).
- *     Strides are in elements.  No transposes.
+ *     Strides are in elements.  gemm_ex adds column-major storage and
+ *     transposed operands.
  *   - Pointers named A, B, C, workspace, arena are DEVICE pointers owned by
  *     the caller; the library never frees caller memory.  Pointers prefixed
  *     h (hA, hC_out, ...) are host pointers.
@@ -132,7 +133,7 @@ gemm_status split_bf16x3(int64_t n, const float *x, uint16_t *p0, uint16_t *p1,
  * The quantised operands and scales live in a caller-provided device
  * workspace of at least gemm_fp8_workspace_bytes(M,N,K) bytes, laid out as
  * [qa: M x Kp bytes][qb^T: N x Kp bytes][sa: M floats][sb: N floats]
- * [N uint32 of scratch], each region 256-byte aligned, Kp = K rounded up to a
+ * [max(M,N) uint32 of scratch], each region 256-byte aligned, Kp = K rounded up to a
  * multiple of 128 (the padding holds zero codes).  qb is stored transposed
  * (column j of B contiguous).  Codes are E4M3 bit patterns (sign, 4 exponent
  * bits with bias 7, 3 mantissa bits; 0x7E = 448, no infinities).
@@ -185,6 +186,45 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
                             const float *A, int64_t lda, const float *B, int64_t ldb,
                             float beta, float *C, int64_t ldc, int n_products,
                             void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Storage order and transposed operands, BLAS style.  The external-code call
+ * of the paper (Sec. 2.1) passes a storage order and transpose flags with its
+ * matrix product; gemm_ex accepts them:
+ *
+ *        C <- alpha * op(A) * op(B) + beta * C,   op(X) = X or X^T,
+ *
+ * op(A) is M x K, op(B) is K x N, C is M x N, each stored in `order`
+ * (GEMM_ROW_MAJOR: element (r, c) at r*ld + c; GEMM_COL_MAJOR: at c*ld + r).
+ * With trans_a == GEMM_TRANS, A is stored as the K x M matrix A^T, likewise
+ * B as N x K (GEMM_CONJ_TRANS is the same for real data).  Leading
+ * dimensions bound the stored row (row-major) or column (column-major)
+ * length: lda >= max(1, stored extent of A along its contiguous index), and
+ * so on: row-major lda >= K (no trans) or M (trans), ldb >= N or K, ldc >= N;
+ * column-major lda >= M or K, ldb >= K or N, ldc >= M.  The values of the
+ * enumerators are those of CBLAS.
+ * A column-major call is the row-major product C^T = op(B)^T op(A)^T with the
+ * operands exchanged; no data is moved.  Transposed operands change only how
+ * tiles are staged into LDS, not the arithmetic: a row-major call with both
+ * flags GEMM_NO_TRANS returns the same bits as gemm_f32 / gemm_f32_3xbf16 /
+ * gemm_fp8_scaled.
+ * path: GEMM_PATH_F32 (binary32 products; transposed operands run on the FP32
+ * matrix-core tiles), GEMM_PATH_3XBF16 (n_products 3 or 6) or GEMM_PATH_FP8
+ * (workspace of at least gemm_fp8_workspace_bytes(M, N, K) bytes, 256-byte
+ * aligned; ignored, and may be NULL, on the other paths).
+ * Arguments: 1 order, 2 trans_a, 3 trans_b, 4 M, 5 N, 6 K, 7 alpha, 8 A,
+ * 9 lda, 10 B, 11 ldb, 12 beta, 13 C, 14 ldc, 15 path, 16 n_products,
+ * 17 workspace, 18 ws_bytes, 19 stream.
+ * ---------------------------------------------------------------------- */
+#define GEMM_ROW_MAJOR   101
+#define GEMM_COL_MAJOR   102
+#define GEMM_NO_TRANS    111
+#define GEMM_TRANS       112
+#define GEMM_CONJ_TRANS  113
+gemm_status gemm_ex(int order, int trans_a, int trans_b, int64_t M, int64_t N, int64_t K,
+                    float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+                    float beta, float *C, int64_t ldc, int path, int n_products,
+                    void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Grouped GEMM: many independent problems of uneven sizes in ONE persistent

@@ -72,6 +72,8 @@ _sig("gemm_fp8_scaled", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32
 _sig("fp8_quantize", _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
 _sig("gemm_fp8_prequantized", _int, _i64, _i64, _i64, _f32, _vp, _sz, _f32, _vp, _i64, _vp)
 _sig("fp8_e4m3_encode", _int, _i64, _vp, _vp, _vp)
+_sig("gemm_ex", _int, _int, _int, _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp,
+     _i64, _int, _int, _vp, _sz, _vp)
 
 
 class gemm_problem(ctypes.Structure):
@@ -220,6 +222,15 @@ def fp8_workspace_layout(M, N, K):
 
 
 PATH_F32, PATH_3XBF16, PATH_FP8, PATH_FP8_PREQUANTIZED = 0, 1, 2, 3
+ROW_MAJOR, COL_MAJOR = 101, 102
+NO_TRANS, TRANS, CONJ_TRANS = 111, 112, 113
+
+
+def gemm_ex(order, trans_a, trans_b, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+            path=PATH_3XBF16, n_products=3, workspace=None, ws_bytes=0, stream=None):
+    return check(lib.gemm_ex(order, trans_a, trans_b, M, N, K, alpha, ptr(A), lda, ptr(B), ldb,
+                             beta, ptr(C), ldc, path, n_products, ptr(workspace), ws_bytes,
+                             stream_handle(stream)))
 
 
 def problem_array(problems):

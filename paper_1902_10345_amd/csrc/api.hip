@@ -323,6 +323,70 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
   }
 }
 
+gemm_status gemm_ex(int order, int trans_a, int trans_b, int64_t M, int64_t N, int64_t K,
+                    float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+                    float beta, float *C, int64_t ldc, int path, int n_products, void *workspace,
+                    size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_ex";
+  if (order != GEMM_ROW_MAJOR && order != GEMM_COL_MAJOR) return bad_arg(1, fn, "(order) unknown");
+  auto is_trans = [](int t) { return t == GEMM_TRANS || t == GEMM_CONJ_TRANS; };
+  if (trans_a != GEMM_NO_TRANS && !is_trans(trans_a)) return bad_arg(2, fn, "(trans_a) unknown");
+  if (trans_b != GEMM_NO_TRANS && !is_trans(trans_b)) return bad_arg(3, fn, "(trans_b) unknown");
+  const bool ta = is_trans(trans_a), tb = is_trans(trans_b);
+  if (M < 0) return bad_arg(4, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(5, fn, "(N) must be >= 0");
+  if (K < 0) return bad_arg(6, fn, "(K) must be >= 0");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL)
+    return bad_arg(M > 0x7fffffffLL ? 4 : N > 0x7fffffffLL ? 5 : 6, fn, "exceeds 2^31-1");
+  // Stored extents along the contiguous index: row-major op(A) = A is M x K
+  // (row length K), A^T is stored K x M (row length M); column-major swaps
+  // the roles of rows and columns.
+  const bool row = order == GEMM_ROW_MAJOR;
+  const int64_t min_lda = row ? (ta ? M : K) : (ta ? K : M);
+  const int64_t min_ldb = row ? (tb ? K : N) : (tb ? N : K);
+  const int64_t min_ldc = row ? N : M;
+  if (lda < (min_lda > 1 ? min_lda : 1)) return bad_arg(9, fn, "(lda) below the stored row length");
+  if (ldb < (min_ldb > 1 ? min_ldb : 1)) return bad_arg(11, fn, "(ldb) below the stored row length");
+  if (ldc < (min_ldc > 1 ? min_ldc : 1)) return bad_arg(14, fn, "(ldc) below the stored row length");
+  if (path != GEMM_PATH_F32 && path != GEMM_PATH_3XBF16 && path != GEMM_PATH_FP8)
+    return bad_arg(15, fn, "(path) must be GEMM_PATH_F32, GEMM_PATH_3XBF16 or GEMM_PATH_FP8");
+  if (path == GEMM_PATH_3XBF16 && n_products != 3 && n_products != 6)
+    return bad_arg(16, fn, "(n_products) must be 3 or 6");
+  if (M == 0 || N == 0) return GEMM_STATUS_OK;
+  if (!C) return bad_arg(13, fn, "(C) is NULL");
+  // Column-major C (M x N) is row-major C^T (N x M) = op(B)^T op(A)^T: the
+  // operands swap places and each keeps its transpose flag.
+  GemmArgs g = row ? GemmArgs{M, N, K, alpha, beta, A, lda, B, ldb, C, ldc}
+                   : GemmArgs{N, M, K, alpha, beta, B, ldb, A, lda, C, ldc};
+  g.ta = row ? ta : tb;
+  g.tb = row ? tb : ta;
+  if (alpha == 0.0f || K == 0) return scale_c(g.M, g.N, beta, C, ldc, stream);
+  if (!A) return bad_arg(8, fn, "(A) is NULL");
+  if (!B) return bad_arg(10, fn, "(B) is NULL");
+  if (path == GEMM_PATH_FP8) {
+    gemm_status st = fp8_check_ws(fn, 17, g.M, g.N, K, workspace, ws_bytes);
+    if (st) return st;
+    if ((st = fp8_quantize_run(g.M, g.N, K, g.A, g.lda, g.B, g.ldb, workspace, stream, g.ta, g.tb)))
+      return st;
+    return fp8_gemm_run_cfg(g.M, g.N, K, alpha, workspace, beta, C, ldc,
+                            pick_config(GEMM_PATH_FP8, 3, g.M, g.N, K), stream);
+  }
+  const bool trans = g.ta || g.tb;
+  if (path == GEMM_PATH_F32) {
+    // transposed operands run on the FP32 matrix-core tiles only
+    int cfg = pick_config(GEMM_PATH_F32, 0, g.M, g.N, K);
+    if (trans && cfg != 5 && cfg != 6) {
+      const int64_t big = ((g.M + 255) / 256) * ((g.N + 255) / 256);
+      cfg = big >= num_cus() ? 5 : 6;
+    }
+    return f32_run(g, cfg, stream);
+  }
+  const int cfg = trans ? bx3_default_config(g.M, g.N, K, n_products)
+                        : pick_config(GEMM_PATH_3XBF16, n_products, g.M, g.N, K);
+  return bx3_run(g, cfg, stream);
+}
+
 size_t err_norm_workspace_bytes(void) { return errnorm_ws_bytes(); }
 
 gemm_status err_norm_f64(int64_t M, int64_t N, const float *C, int64_t ldc, const double *Cref,

@@ -78,10 +78,6 @@ struct Cfg {
   // MFMA k-steps per slab: 16 k (bf16 planes) or 8 k (FP32 mode: two 4-k
   // chunks per lane pair, each feeding four 32x32x2 MFMAs)
   static constexpr int KS = NP == 1 ? BK / 8 : BK / 16;
-  static constexpr int A_ITEMS = BM * CH / NT;    // (row, chunk) items per lane
-  static constexpr int B_ITEMS = BN * CH / NT;    // (col, chunk) items per lane
-  static_assert(A_ITEMS * NT == BM * CH && B_ITEMS * NT == BN * CH, "even split");
-  static_assert(BN % 64 == 0 || NT % BN == 0, "B chunk index must be wave-uniform");
   static constexpr int PLANE_A = BM * BK;     // bf16 elements per A plane
   static constexpr int PLANE_B = BN * BK;
   static constexpr int STAGE = NPL * (PLANE_A + PLANE_B);  // bf16 units per stage
@@ -92,19 +88,158 @@ struct Cfg {
   static constexpr int SETS = BK >= 32 ? 1 : 2;
 };
 
+// Staging of one operand slab into LDS: ROWS LDS rows (the rows of A's tile
+// or the columns of B's tile), each BK deep in k, moved as items of 8
+// consecutive k per lane.
+//   KC (k contiguous in memory: row-major A, transposed B): item idx covers
+//      LDS row idx / CH, chunk idx % CH; two 128-bit loads when V (row stride
+//      a multiple of 4 floats, 16-byte aligned base), else eight 32-bit loads.
+//   otherwise (the row index contiguous: row-major B, transposed A): item idx
+//      covers LDS row idx % ROWS, chunk idx / ROWS; eight 32-bit loads, one
+//      per k, with the lanes of a wave consecutive along the row index.
+// Either way the LDS layout is the same ([plane][ROWS][BK], swizzled chunks),
+// so the fragment reads and the MFMAs do not depend on the memory layout.
+template <int ROWS, int BK, int NT, int SETS, bool KC, bool V>
+struct Stage {
+  static constexpr int CH = BK / 8;
+  static constexpr int ITEMS = ROWS * CH / NT;
+  static_assert(ITEMS * NT == ROWS * CH, "even split of the slab over the lanes");
+  static_assert(KC || ROWS % 64 == 0 || NT % ROWS == 0, "chunk index must be wave-uniform");
+  // global loads per slab and lane
+  static constexpr int LOADS = ITEMS * ((KC && V) ? 2 : 8);
+  __device__ static __forceinline__ int row_of(int idx) { return KC ? idx / CH : idx % ROWS; }
+  __device__ static __forceinline__ int chunk_of(int idx) { return KC ? idx % CH : idx / ROWS; }
+
+  float r[SETS][ITEMS][8];
+  // KC: byte offset of the item's (row, chunk) inside the tile's panel at k 0.
+  // Otherwise: byte offset of the item's row index inside a k row (rows past
+  // the matrix get an offset beyond any slab resource, so they read as zero).
+  int voff[ITEMS];
+  int soff[ITEMS];  // otherwise: wave-uniform byte offset of the item's first k row
+  __amdgpu_buffer_rsrc_t rsrc;  // KC: the tile's panel
+  const float *P;
+  int64_t ld;
+  int r0, nrows, K;
+
+  // P: the operand as stored; ld: its row stride; r0: the tile's first LDS
+  // row (output row of A / column of B); total: rows (KC) or row-index extent.
+  __device__ __forceinline__ void init(const float *P_, int64_t ld_, int r0_, int total, int K_,
+                                       int tid) {
+    P = P_; ld = ld_; r0 = r0_; K = K_;
+    nrows = total - r0 < ROWS ? total - r0 : ROWS;
+    if constexpr (KC) {
+      // valid bytes end with the last valid row's K elements: reads past the
+      // matrix (rows beyond it, k beyond K of the last row) return zero
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(P + (int64_t)r0 * ld), (short)0,
+          nrows > 0 ? (int)(((int64_t)(nrows - 1) * ld + K) * 4) : 0, kBufferFlags);
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        voff[i] = (row_of(idx) * (int)ld + chunk_of(idx) * 8) * 4;
+      }
+    } else {
+      const int ld4 = (int)ld * 4;
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int idx = tid + NT * i;
+        const int n = row_of(idx);
+        voff[i] = n < nrows ? n * 4 : (int)0x80000000;
+        soff[i] = __builtin_amdgcn_readfirstlane(8 * chunk_of(idx)) * ld4;
+      }
+    }
+  }
+
+  // FAST: every k of the slab lies in [0, K) (or the data is never consumed).
+  // Otherwise k outside [0, K) read as zero.
+  template <int SET, bool FAST>
+  __device__ __forceinline__ void load(int k0) {
+    if constexpr (KC) {
+      if constexpr (FAST) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const int off = voff[i] + k0 * 4;
+          if constexpr (V) {
+            // (bit-cast whole vectors: a bit_cast of a vector element is not
+            // element-indexed in this compiler)
+            const float4 v0 =
+                __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+            const float4 v1 =
+                __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, 0));
+            r[SET][i][0] = v0.x; r[SET][i][1] = v0.y; r[SET][i][2] = v0.z; r[SET][i][3] = v0.w;
+            r[SET][i][4] = v1.x; r[SET][i][5] = v1.y; r[SET][i][6] = v1.z; r[SET][i][7] = v1.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              r[SET][i][e] = __builtin_bit_cast(
+                  float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off + 4 * e, 0, 0));
+          }
+        }
+      } else {  // partial slab: per-element offsets, invalid ones pushed out of range
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const int k = k0 + chunk_of((int)threadIdx.x + NT * i) * 8;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int off = (k + e >= 0 && k + e < K) ? voff[i] + (k0 + e) * 4 : (int)0x80000000;
+            r[SET][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0));
+          }
+        }
+      }
+    } else {
+      const int ld4 = (int)ld * 4;
+      if constexpr (FAST) {
+        // one resource for the whole slab; per-lane offsets select the rows
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(P + (int64_t)(k0 > 0 ? k0 : 0) * ld + r0), (short)0,
+            k0 >= 0 ? (int)(((int64_t)(BK - 1) * ld + nrows) * 4) : 0, kBufferFlags);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            r[SET][i][e] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff[i], soff[i] + e * ld4, 0));
+      } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const int idx = (int)threadIdx.x + NT * i;
+          const int n = row_of(idx);
+          const int c = __builtin_amdgcn_readfirstlane(chunk_of(idx));  // wave-uniform
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            // one resource per k row: rows outside [0, K) have no valid bytes,
+            // row indices at or past the extent fall beyond the row's valid bytes
+            const int k = k0 + 8 * c + e;
+            const bool kin = k >= 0 && k < K;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float *>(P + (int64_t)(kin ? k : 0) * ld + r0), (short)0,
+                kin ? nrows * 4 : 0, kBufferFlags);
+            r[SET][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, n * 4, 0, 0));
+          }
+        }
+      }
+    }
+  }
+};
+
 // One output tile.  lds must hold Cfg::LDS_BYTES bytes (16-byte aligned).
-// VEC: lda % 4 == 0 and A 16-byte aligned (128-bit loads of A rows).
+// TA / TB: A / B are given transposed (A stored K x M with row stride lda,
+// B stored N x K with row stride ldb); op(A) op(B) is computed either way.
+// VEC: every operand stored with k contiguous (A unless TA, B if TB) has a
+// row stride that is a multiple of 4 floats and a 16-byte aligned base
+// (128-bit loads), and K % 4 == 0.
 // Interior slabs (tile fully inside M x N and a whole BK slab of K) take an
 // unpredicated load path; edge slabs take a guarded path that reads zeros
 // outside the matrices.  The choice is uniform across the workgroup.
-template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA>
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA,
+          bool TA = false, bool TB = false>
 __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
                                      const float *__restrict__ A, int64_t lda,
                                      const float *__restrict__ B, int64_t ldb, float beta,
                                      float *__restrict__ C, int64_t ldc, int m0, int n0,
                                      __bf16 *lds) {
   using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
-  constexpr int NT = G::NT, CH = G::CH;
+  constexpr int NT = G::NT;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int Mr = M - m0, Nr = N - n0;
@@ -112,102 +247,21 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   // Staging loads are raw buffer loads: the resource holds the tile's base
   // address and the number of valid bytes, so reads past the matrix return
   // zero in hardware and lane addresses stay 32-bit offsets (no 64-bit VALU
-  // address arithmetic).  The launcher guarantees (BM * lda + K) * 4 < 2^31.
-  const int rowsA = Mr < BM ? Mr : BM;
-  const __amdgpu_buffer_rsrc_t rsrcA = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float *>(A + (int64_t)m0 * lda), (short)0,
-      rowsA > 0 ? (int)(((int64_t)(rowsA - 1) * lda + K) * 4) : 0, kBufferFlags);
-  const int colsB = Nr < BN ? Nr : BN;
-  // byte offsets of this lane's A items inside the tile's row panel, slab 0
-  int a_voff[G::A_ITEMS];
-#pragma unroll
-  for (int i = 0; i < G::A_ITEMS; ++i) {
-    const int idx = tid + NT * i;
-    a_voff[i] = ((idx / CH) * (int)lda + (idx % CH) * 8) * 4;
-  }
-  // B items: this lane's column (a byte offset inside a slab row; columns
-  // past N get an offset beyond any slab resource, so they read as zero) and
-  // the item's first row of the slab (wave-uniform, a scalar offset)
-  int b_vcol[G::B_ITEMS], b_srow[G::B_ITEMS];
-  const int ldb4 = (int)ldb * 4;
-#pragma unroll
-  for (int i = 0; i < G::B_ITEMS; ++i) {
-    const int idx = tid + NT * i;
-    const int n = idx % BN;
-    b_vcol[i] = n < colsB ? n * 4 : (int)0x80000000;
-    b_srow[i] = __builtin_amdgcn_readfirstlane(8 * (idx / BN)) * ldb4;
-  }
+  // address arithmetic).  The launcher guarantees that every panel's and
+  // slab's byte extent stays below 2^31.
+  using SA = Stage<BM, BK, NT, G::SETS, !TA, VEC && !TA>;
+  using SB = Stage<BN, BK, NT, G::SETS, TB, VEC && TB>;
+  SA sa;
+  SB sb;
+  sa.init(A, lda, m0, M, K, tid);
+  sb.init(B, ldb, n0, N, K, tid);
 
-  // ---- global -> registers (two register sets, selected at compile time) --
-  float ra[G::SETS][G::A_ITEMS][8];
-  float rb[G::SETS][G::B_ITEMS][8];
-  // FAST: every element of the slab lies in [0, K) (or the data is never
-  // consumed).  Otherwise elements outside [0, K) read as zero.
+  // ---- global -> registers (register sets selected at compile time) --------
   auto gload = [&](auto S, auto F, int k0) {
     constexpr int set = decltype(S)::value;
     constexpr bool FAST = decltype(F)::value;
-    if (FAST) {
-#pragma unroll
-      for (int i = 0; i < G::A_ITEMS; ++i) {
-        const int off = a_voff[i] + k0 * 4;
-        if (VEC) {
-          // (bit-cast whole vectors: a bit_cast of a vector element is not
-          // element-indexed in this compiler)
-          const float4 v0 =
-              __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrcA, off, 0, 0));
-          const float4 v1 =
-              __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrcA, off + 16, 0, 0));
-          ra[set][i][0] = v0.x; ra[set][i][1] = v0.y; ra[set][i][2] = v0.z; ra[set][i][3] = v0.w;
-          ra[set][i][4] = v1.x; ra[set][i][5] = v1.y; ra[set][i][6] = v1.z; ra[set][i][7] = v1.w;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            ra[set][i][e] = __builtin_bit_cast(
-                float, __builtin_amdgcn_raw_buffer_load_b32(rsrcA, off + 4 * e, 0, 0));
-        }
-      }
-    } else {  // partial slab: per-element offsets, invalid ones pushed out of range
-#pragma unroll
-      for (int i = 0; i < G::A_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int k = k0 + (idx % CH) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int off = (k + e >= 0 && k + e < K) ? a_voff[i] + (k0 + e) * 4 : (int)0x80000000;
-          ra[set][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrcA, off, 0, 0));
-        }
-      }
-    }
-    if (FAST) {
-      // one resource for the whole slab; per-lane offsets select the rows
-      const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<float *>(B + (int64_t)(k0 > 0 ? k0 : 0) * ldb + n0), (short)0,
-          k0 >= 0 ? (int)(((int64_t)(BK - 1) * ldb + colsB) * 4) : 0, kBufferFlags);
-#pragma unroll
-      for (int i = 0; i < G::B_ITEMS; ++i)
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          rb[set][i][e] = __builtin_bit_cast(
-              float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, b_vcol[i], b_srow[i] + e * ldb4, 0));
-    } else {
-#pragma unroll
-      for (int i = 0; i < G::B_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int n = idx % BN;
-        const int c = __builtin_amdgcn_readfirstlane(idx / BN);  // wave-uniform
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          // one resource per B row: rows outside [0, K) have no valid bytes,
-          // columns at or past N fall beyond the row's valid bytes
-          const int k = k0 + 8 * c + e;
-          const bool kin = k >= 0 && k < K;
-          const __amdgpu_buffer_rsrc_t rsrcB = __builtin_amdgcn_make_buffer_rsrc(
-              const_cast<float *>(B + (int64_t)(kin ? k : 0) * ldb + n0), (short)0,
-              kin ? colsB * 4 : 0, kBufferFlags);
-          rb[set][i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrcB, n * 4, 0, 0));
-        }
-      }
-    }
+    sa.template load<set, FAST>(k0);
+    sb.template load<set, FAST>(k0);
   };
 
   // ---- split + registers -> LDS --------------------------------------------
@@ -222,55 +276,36 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       if constexpr (NP == 3) l[e] = x2;
     }
   };
-  auto sstore = [&](auto S, int stage) {
+  // One operand's items into its LDS planes (row-major [plane][ROWS][ROW]).
+  auto store_op = [&](auto &op, auto S, __bf16 *base, auto PL) {
+    using Op = std::remove_reference_t<decltype(op)>;
     constexpr int set = decltype(S)::value;
-    __bf16 *sA = lds + stage * G::STAGE;
-    __bf16 *sB = sA + G::NPL * G::PLANE_A;
-    if constexpr (NP == 1) {  // FP32 mode: the item's 8 values as two 16-byte chunks
+    constexpr int PLANE = decltype(PL)::value;
 #pragma unroll
-      for (int i = 0; i < G::A_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int r = idx / CH, c = idx % CH;
-        const float *x = ra[set][i];
-        *reinterpret_cast<f32x4 *>(sA + r * G::ROW + (((2 * c) ^ swz<G::ROW>(r)) << 3)) =
+    for (int i = 0; i < Op::ITEMS; ++i) {
+      const int idx = tid + NT * i;
+      const int r = Op::row_of(idx), c = Op::chunk_of(idx);
+      const float *x = op.r[set][i];
+      if constexpr (NP == 1) {  // FP32 mode: the item's 8 values as two 16-byte chunks
+        *reinterpret_cast<f32x4 *>(base + r * G::ROW + (((2 * c) ^ swz<G::ROW>(r)) << 3)) =
             f32x4{x[0], x[1], x[2], x[3]};
-        *reinterpret_cast<f32x4 *>(sA + r * G::ROW + (((2 * c + 1) ^ swz<G::ROW>(r)) << 3)) =
+        *reinterpret_cast<f32x4 *>(base + r * G::ROW + (((2 * c + 1) ^ swz<G::ROW>(r)) << 3)) =
             f32x4{x[4], x[5], x[6], x[7]};
-      }
-#pragma unroll
-      for (int i = 0; i < G::B_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int n = idx % BN, c = idx / BN;
-        const float *x = rb[set][i];
-        *reinterpret_cast<f32x4 *>(sB + n * G::ROW + (((2 * c) ^ swz<G::ROW>(n)) << 3)) =
-            f32x4{x[0], x[1], x[2], x[3]};
-        *reinterpret_cast<f32x4 *>(sB + n * G::ROW + (((2 * c + 1) ^ swz<G::ROW>(n)) << 3)) =
-            f32x4{x[4], x[5], x[6], x[7]};
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < G::A_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int r = idx / CH, c = idx % CH;
+      } else {
         bf16x8 h, m, l;
-        split8(ra[set][i], h, m, l);
+        split8(op.r[set][i], h, m, l);
         const int off = r * BK + ((c ^ swz<BK>(r)) << 3);
-        *reinterpret_cast<bf16x8 *>(sA + off) = h;
-        *reinterpret_cast<bf16x8 *>(sA + G::PLANE_A + off) = m;
-        if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sA + 2 * G::PLANE_A + off) = l;
-      }
-#pragma unroll
-      for (int i = 0; i < G::B_ITEMS; ++i) {
-        const int idx = tid + NT * i;
-        const int n = idx % BN, c = idx / BN;
-        bf16x8 h, m, l;
-        split8(rb[set][i], h, m, l);
-        const int off = n * BK + ((c ^ swz<BK>(n)) << 3);
-        *reinterpret_cast<bf16x8 *>(sB + off) = h;
-        *reinterpret_cast<bf16x8 *>(sB + G::PLANE_B + off) = m;
-        if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(sB + 2 * G::PLANE_B + off) = l;
+        *reinterpret_cast<bf16x8 *>(base + off) = h;
+        *reinterpret_cast<bf16x8 *>(base + PLANE + off) = m;
+        if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(base + 2 * PLANE + off) = l;
       }
     }
+  };
+  auto sstore = [&](auto S, int stage) {
+    __bf16 *sA = lds + stage * G::STAGE;
+    __bf16 *sB = sA + G::NPL * G::PLANE_A;
+    store_op(sa, S, sA, std::integral_constant<int, G::PLANE_A>{});
+    store_op(sb, S, sB, std::integral_constant<int, G::PLANE_B>{});
   };
 
   // ---- MFMA over one slab ------------------------------------------------
@@ -456,8 +491,8 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
     static_assert(G::KS == 1, "two register sets are used with 16-deep slabs");
     constexpr int kMfma = G::FM * G::FN * (NP == 2 ? 3 : 6);
     constexpr int kReads = (G::FM + G::FN) * NP;
-    constexpr int kLoads = G::A_ITEMS * (VEC ? 2 : 8) + G::B_ITEMS * 8;
-    constexpr int kWrites = (G::A_ITEMS + G::B_ITEMS) * NP;
+    constexpr int kLoads = SA::LOADS + SB::LOADS;
+    constexpr int kWrites = (SA::ITEMS + SB::ITEMS) * NP;
     constexpr int kLoadSlots = kLoads < kMfma ? kLoads : kMfma;
     auto step = [&](auto LS, int kload, int mstage, auto SS, int sstage) {
       gload(LS, Fast{}, kload);

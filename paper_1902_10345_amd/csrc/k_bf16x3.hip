@@ -1,90 +1,10 @@
 // k_bf16x3.hip -- FP32-accurate split-precision GEMM on bf16 MFMA (gfx950).
 #include <algorithm>
 
-#include "bf16x3.hpp"
+#include "bx3_launch.hpp"
 
 namespace mm {
 namespace bx3 {
-
-template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA>
-__global__ __launch_bounds__(64 * NW, 1) void gemm_bx3_kernel(
-    int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda,
-    const float *__restrict__ B, int64_t ldb, float beta, float *__restrict__ C, int64_t ldc,
-    int tiles_m, int tiles_n) {
-  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
-  __shared__ __attribute__((aligned(16))) __bf16 lds[G::LDS_BYTES / 2];
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  int tm, tn;
-  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
-  tile<BM, BN, BK, WM, WN, NP, NW, VEC, BETA>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                         tm * BM, tn * BN, lds);
-}
-
-// The plain binary32 product on the FP32 matrix cores (v_mfma_f32_32x32x2f32):
-// the same tile body in its FP32 mode (no split; binary32 in LDS).
-template <int BM, int BN, int BK, int WM, int WN, int NW, bool VEC, bool BETA>
-__global__ __launch_bounds__(64 * NW, 1) void gemm_f32mfma_kernel(
-    int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda,
-    const float *__restrict__ B, int64_t ldb, float beta, float *__restrict__ C, int64_t ldc,
-    int tiles_m, int tiles_n) {
-  using G = Cfg<BM, BN, BK, WM, WN, 1, NW>;
-  __shared__ __attribute__((aligned(16))) __bf16 lds[G::LDS_BYTES / 2];
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  int tm, tn;
-  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
-  tile<BM, BN, BK, WM, WN, 1, NW, VEC, BETA>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                         tm * BM, tn * BN, lds);
-}
-
-template <int BM, int BN, int BK, int WM, int WN, int NW>
-gemm_status launch_f32mfma(const GemmArgs &g, hipStream_t s) {
-  const int tiles_m = (int)((g.M + BM - 1) / BM);
-  const int tiles_n = (int)((g.N + BN - 1) / BN);
-  const int64_t nwg = (int64_t)tiles_m * tiles_n;
-  if (nwg > 0x7fffffff) { set_error("gemm_f32: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
-  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 ||
-      ((int64_t)BK * g.ldb + g.N) * 4 >= ((int64_t)1 << 31)) {
-    set_error("gemm_f32: lda or ldb too large for 32-bit tile offsets");
-    return GEMM_STATUS_UNSUPPORTED;
-  }
-  const bool vec = g.lda % 4 == 0 && g.K % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
-  const bool beta = g.beta != 0.0f;
-  dim3 grid((unsigned)nwg), block(64 * NW);
-#define MM_LAUNCH(V, BT)                                                                     \
-  hipLaunchKernelGGL((gemm_f32mfma_kernel<BM, BN, BK, WM, WN, NW, V, BT>), grid, block, 0, s, \
-                     (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta,  \
-                     g.C, g.ldc, tiles_m, tiles_n)
-  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
-  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
-#undef MM_LAUNCH
-  return check_launch("gemm_f32mfma_kernel");
-}
-
-template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
-gemm_status launch(const GemmArgs &g, hipStream_t s) {
-  const int tiles_m = (int)((g.M + BM - 1) / BM);
-  const int tiles_n = (int)((g.N + BN - 1) / BN);
-  const int64_t nwg = (int64_t)tiles_m * tiles_n;
-  if (nwg > 0x7fffffff) { set_error("gemm_f32_3xbf16: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
-  if (((int64_t)BM * g.lda + g.K) * 4 >= (int64_t)1 << 31 ||
-      ((int64_t)BK * g.ldb + g.N) * 4 >= ((int64_t)1 << 31)) {
-    set_error("gemm_f32_3xbf16: lda too large for 32-bit tile offsets");
-    return GEMM_STATUS_UNSUPPORTED;
-  }
-  // 128-bit loads of A rows need 16-byte aligned slab starts: the slab grid
-  // ends at K, so K must be a multiple of 4 as well as lda.
-  const bool vec = g.lda % 4 == 0 && g.K % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
-  const bool beta = g.beta != 0.0f;
-  dim3 grid((unsigned)nwg), block(64 * NW);
-#define MM_LAUNCH(V, BT)                                                                    \
-  hipLaunchKernelGGL((gemm_bx3_kernel<BM, BN, BK, WM, WN, NP, NW, V, BT>), grid, block, 0, s, \
-                     (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, \
-                     g.C, g.ldc, tiles_m, tiles_n)
-  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
-  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
-#undef MM_LAUNCH
-  return check_launch("gemm_bx3_kernel");
-}
 
 // ---- split-K ----------------------------------------------------------------
 // Workgroup (chunk c, output tile) multiplies K range [c*chunk, min(K, (c+1)*chunk))
@@ -240,6 +160,7 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
 }
 
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
+  if (g.ta || g.tb) return g.ta ? (g.tb ? bx3_run_tt(g, cfg, s) : bx3_run_tn(g, cfg, s)) : bx3_run_nt(g, cfg, s);
   switch (cfg) {
     case 0: return bx3::launch<256, 256, 16, 128, 64, 2, 8>(g, s);
     case 1: return bx3::launch<128, 128, 32, 64, 64, 2, 4>(g, s);
@@ -277,6 +198,9 @@ gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *
 }
 
 gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
+  if (g.ta || g.tb)
+    return g.ta ? (g.tb ? f32mfma_run_tt(g, which, s) : f32mfma_run_tn(g, which, s))
+                : f32mfma_run_nt(g, which, s);
   if (which == 0) return bx3::launch_f32mfma<256, 256, 16, 128, 64, 8>(g, s);
   return bx3::launch_f32mfma<128, 128, 16, 64, 64, 4>(g, s);
 }

@@ -273,6 +273,10 @@ int f32_default_config(int64_t M, int64_t N, int64_t K) {
 }
 
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
+  if ((g.ta || g.tb) && cfg != 5 && cfg != 6) {
+    set_error("gemm_ex: only the FP32 matrix-core tiles take transposed operands");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
   switch (cfg) {
     case 0: return f32::launch<128, 128, 32, 8, 8, 1>(g, s);
     case 1: return f32::launch<64, 64, 32, 4, 4, 1>(g, s);

@@ -38,7 +38,8 @@ Layout layout(int64_t M, int64_t N, int64_t K) {
   L.qb = off; off = align256(off + (size_t)(N * L.Kp));
   L.sa = off; off = align256(off + sizeof(float) * (size_t)M);
   L.sb = off; off = align256(off + sizeof(float) * (size_t)N);
-  L.amax = off; off = align256(off + sizeof(uint32_t) * (size_t)N);
+  // column-amax scratch, shared by the column quantisations of both operands
+  L.amax = off; off = align256(off + sizeof(uint32_t) * (size_t)(M > N ? M : N));
   L.total = off;
   return L;
 }
@@ -553,8 +554,64 @@ __global__ __launch_bounds__(256) void encode_kernel(int64_t n, const float *__r
 size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K) { return fp8::layout(M, N, K).total; }
 int64_t fp8_kp(int64_t K) { return fp8::layout(0, 0, K).Kp; }
 
+// Row quantisation: R rows of K binary32 values (row stride ld) -> per-row
+// scales and codes in rows of Kp bytes (k contiguous).
+static gemm_status quant_rows(int64_t R, int64_t K, int64_t Kp, const float *P, int64_t ld,
+                              uint8_t *q, float *scales, hipStream_t s) {
+  const bool vec = ld % 4 == 0 && ((uintptr_t)P & 15) == 0;
+  const int ch = (int)((Kp + 1023) / 1024);
+#define MM_QROWS(CH)                                                                             \
+  do {                                                                                           \
+    if (vec)                                                                                     \
+      hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, true>), dim3((unsigned)R), dim3(256), 0, \
+                         s, (int)R, (int)K, Kp, P, ld, q, scales);                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, false>), dim3((unsigned)R), dim3(256),  \
+                         0, s, (int)R, (int)K, Kp, P, ld, q, scales);                            \
+  } while (0)
+  switch (ch) {
+    case 1: MM_QROWS(1); break;
+    case 2: MM_QROWS(2); break;
+    case 3: MM_QROWS(3); break;
+    case 4: MM_QROWS(4); break;
+    case 5: MM_QROWS(5); break;
+    case 6: MM_QROWS(6); break;
+    case 7: MM_QROWS(7); break;
+    case 8: MM_QROWS(8); break;
+    default:
+      hipLaunchKernelGGL(fp8::quant_rows_kernel, dim3((unsigned)R), dim3(256), 0, s, (int)R,
+                         (int)K, Kp, P, ld, q, scales);
+  }
+#undef MM_QROWS
+  return check_launch("quant_rows_kernel");
+}
+
+// Column quantisation: a K x Nc matrix (row stride ld) -> per-column scales
+// and the codes of each column in a row of Kp bytes (transposed, k
+// contiguous).  amax: Nc words of scratch.
+static gemm_status quant_cols(int64_t K, int64_t Nc, int64_t Kp, const float *P, int64_t ld,
+                              uint32_t *amax, uint8_t *q, float *scales, hipStream_t s) {
+  const unsigned fg = (unsigned)std::min<int64_t>((Nc + 255) / 256, 1024);
+  hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, Nc);
+  if (gemm_status st = check_launch("fill_u32_kernel")) return st;
+  const bool vec = ld % 4 == 0 && ((uintptr_t)P & 15) == 0;
+  const dim3 ag((unsigned)((Nc + 63) / 64), (unsigned)std::max<int64_t>(1, (K + 255) / 256));
+  if (vec)
+    hipLaunchKernelGGL(fp8::col_amax4_kernel<true>, ag, dim3(256), 0, s, (int)K, (int)Nc, P, ld, amax);
+  else
+    hipLaunchKernelGGL(fp8::col_amax4_kernel<false>, ag, dim3(256), 0, s, (int)K, (int)Nc, P, ld, amax);
+  if (gemm_status st = check_launch("col_amax4_kernel")) return st;
+  hipLaunchKernelGGL(fp8::quant_cols_t_kernel, dim3((unsigned)(Kp / 64), (unsigned)((Nc + 63) / 64)),
+                     dim3(256), 0, s, (int)K, (int)Nc, Kp, P, ld, amax, q, scales);
+  return check_launch("quant_cols_t_kernel");
+}
+
+// op(A) (M x K) by rows and op(B) (K x N) by columns.  A row of op(A) is a
+// row of A, or a column of A^T as stored (ta); a column of op(B) is a column
+// of B, or a row of B^T as stored (tb).
 gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
-                             const float *B, int64_t ldb, void *ws, hipStream_t s) {
+                             const float *B, int64_t ldb, void *ws, hipStream_t s, bool ta,
+                             bool tb) {
   const fp8::Layout L = fp8::layout(M, N, K);
   uint8_t *base = static_cast<uint8_t *>(ws);
   uint8_t *qa = base + L.qa;
@@ -563,47 +620,14 @@ gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, in
   float *sb = reinterpret_cast<float *>(base + L.sb);
   uint32_t *amax = reinterpret_cast<uint32_t *>(base + L.amax);
   if (M > 0) {
-    const bool vec = lda % 4 == 0 && ((uintptr_t)A & 15) == 0;
-    const int ch = (int)((L.Kp + 1023) / 1024);
-#define MM_QROWS(CH)                                                                             \
-  do {                                                                                           \
-    if (vec)                                                                                     \
-      hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, true>), dim3((unsigned)M), dim3(256), 0, \
-                         s, (int)M, (int)K, L.Kp, A, lda, qa, sa);                               \
-    else                                                                                         \
-      hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, false>), dim3((unsigned)M), dim3(256),  \
-                         0, s, (int)M, (int)K, L.Kp, A, lda, qa, sa);                            \
-  } while (0)
-    switch (ch) {
-      case 1: MM_QROWS(1); break;
-      case 2: MM_QROWS(2); break;
-      case 3: MM_QROWS(3); break;
-      case 4: MM_QROWS(4); break;
-      case 5: MM_QROWS(5); break;
-      case 6: MM_QROWS(6); break;
-      case 7: MM_QROWS(7); break;
-      case 8: MM_QROWS(8); break;
-      default:
-        hipLaunchKernelGGL(fp8::quant_rows_kernel, dim3((unsigned)M), dim3(256), 0, s, (int)M,
-                           (int)K, L.Kp, A, lda, qa, sa);
-    }
-#undef MM_QROWS
-    if (gemm_status st = check_launch("quant_rows_kernel")) return st;
+    gemm_status st = ta ? quant_cols(K, M, L.Kp, A, lda, amax, qa, sa, s)
+                        : quant_rows(M, K, L.Kp, A, lda, qa, sa, s);
+    if (st) return st;
   }
   if (N > 0) {
-    const unsigned fg = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
-    hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, N);
-    if (gemm_status st = check_launch("fill_u32_kernel")) return st;
-    const bool vec = ldb % 4 == 0 && ((uintptr_t)B & 15) == 0;
-    const dim3 ag((unsigned)((N + 63) / 64), (unsigned)std::max<int64_t>(1, (K + 255) / 256));
-    if (vec)
-      hipLaunchKernelGGL(fp8::col_amax4_kernel<true>, ag, dim3(256), 0, s, (int)K, (int)N, B, ldb, amax);
-    else
-      hipLaunchKernelGGL(fp8::col_amax4_kernel<false>, ag, dim3(256), 0, s, (int)K, (int)N, B, ldb, amax);
-    if (gemm_status st = check_launch("col_amax4_kernel")) return st;
-    hipLaunchKernelGGL(fp8::quant_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)((N + 63) / 64)),
-                       dim3(256), 0, s, (int)K, (int)N, L.Kp, B, ldb, amax, qb, sb);
-    if (gemm_status st = check_launch("quant_cols_t_kernel")) return st;
+    gemm_status st = tb ? quant_rows(N, K, L.Kp, B, ldb, qb, sb, s)
+                        : quant_cols(K, N, L.Kp, B, ldb, amax, qb, sb, s);
+    if (st) return st;
   }
   return GEMM_STATUS_OK;
 }

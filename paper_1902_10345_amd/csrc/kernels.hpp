@@ -5,7 +5,9 @@
 
 namespace mm {
 
-// One GEMM problem after argument checking: C <- alpha*A*B + beta*C.
+// One GEMM problem after argument checking: C <- alpha*op(A)*op(B) + beta*C,
+// row-major.  ta: A is stored K x M (row stride lda), op(A) = A^T; tb: B is
+// stored N x K (row stride ldb), op(B) = B^T.
 struct GemmArgs {
   int64_t M, N, K;
   float alpha, beta;
@@ -15,6 +17,7 @@ struct GemmArgs {
   int64_t ldb;
   float *C;
   int64_t ldc;
+  bool ta = false, tb = false;
 };
 
 struct TileConfig {
@@ -34,6 +37,14 @@ const TileConfig &bx3_config(int i);
 int bx3_config_products(int i);
 int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products);
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s);
+// Transposed-operand variants (B^T, A^T, both), for configurations 3, 4, 5,
+// 6 and 8; bx3_run and f32mfma_run dispatch to them from g.ta / g.tb.
+gemm_status bx3_run_nt(const GemmArgs &g, int cfg, hipStream_t s);
+gemm_status bx3_run_tn(const GemmArgs &g, int cfg, hipStream_t s);
+gemm_status bx3_run_tt(const GemmArgs &g, int cfg, hipStream_t s);
+gemm_status f32mfma_run_nt(const GemmArgs &g, int which, hipStream_t s);
+gemm_status f32mfma_run_tn(const GemmArgs &g, int which, hipStream_t s);
+gemm_status f32mfma_run_tt(const GemmArgs &g, int which, hipStream_t s);
 int bx3_splitk_default(int64_t M, int64_t N, int64_t K);
 // FP32 matrix-core tiles of the plain path: 0 = 256 x 256 (8 waves), 1 = 128 x 128 (4 waves)
 gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s);
@@ -45,8 +56,10 @@ gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uin
 // Scaled FP8 path.
 size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K);
 int64_t fp8_kp(int64_t K);
+// ta / tb: A stored K x M (op(A) = A^T), B stored N x K (op(B) = B^T).
 gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
-                             const float *B, int64_t ldb, void *ws, hipStream_t s);
+                             const float *B, int64_t ldb, void *ws, hipStream_t s,
+                             bool ta = false, bool tb = false);
 int fp8_num_configs();
 int fp8_default_config(int64_t M, int64_t N, int64_t K);
 const char *fp8_config_name(int cfg);

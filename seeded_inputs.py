@@ -80,12 +80,15 @@ def storage(x: np.ndarray, order: str, ld: int, pad_value: float = float("nan"))
 
 
 def unstorage(buf: np.ndarray, order: str, rows: int, cols: int, ld: int) -> np.ndarray:
-    """Inverse of storage(): the rows x cols matrix held in a flat buffer."""
+    """Inverse of storage(): the rows x cols matrix held in a flat buffer (a
+    C-contiguous copy)."""
     if order == "C":
-        return np.asarray(buf[:rows * ld]).reshape(rows, ld, order="C")[:, :cols] if rows else \
+        x = np.asarray(buf[:rows * ld]).reshape(rows, ld, order="C")[:, :cols] if rows else \
             np.zeros((0, cols), np.float32)
-    return np.asarray(buf[:cols * ld]).reshape(ld, cols, order="F")[:rows, :] if cols else \
-        np.zeros((rows, 0), np.float32)
+    else:
+        x = np.asarray(buf[:cols * ld]).reshape(ld, cols, order="F")[:rows, :] if cols else \
+            np.zeros((rows, 0), np.float32)
+    return np.ascontiguousarray(x)
 
 
 def outlier_columns(n_cols: int, frac: float, seed: int) -> np.ndarray:

@@ -192,3 +192,56 @@ def test_splitk_argument_codes_and_sizes():
         assert mm.gemm_splitk_workspace_bytes(M, N, K, 0) == mm.gemm_splitk_workspace_bytes(M, N, K, s)
     assert mm.gemm_splitk_default_splits(4096, 4096, 4096) == 1
     assert mm.gemm_splitk_default_splits(64, 4096, 4096) == 16
+
+
+def test_gemm_ex_argument_codes():
+    """Storage order, transpose flags and leading dimensions are checked
+    before anything is enqueued (these calls never reach the device)."""
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    R, Cm, Nt, T = mm.ROW_MAJOR, mm.COL_MAJOR, mm.NO_TRANS, mm.TRANS
+    M, N, K = 4, 8, 16
+
+    def call(order=R, ta=Nt, tb=Nt, M=M, N=N, K=K, A=F, lda=None, B=F, ldb=None, C=F, ldc=None,
+             path=mm.PATH_3XBF16, n=3, ws=None, nb=0, alpha=1.0):
+        row = order == R
+        lda = lda if lda is not None else ((M if ta == T else K) if row else (K if ta == T else M))
+        ldb = ldb if ldb is not None else ((K if tb == T else N) if row else (N if tb == T else K))
+        ldc = ldc if ldc is not None else (N if row else M)
+        return lib.gemm_ex(order, ta, tb, M, N, K, alpha, A, lda, B, ldb, 0.0, C, ldc, path, n, ws,
+                           nb, None)
+
+    assert call(order=100) == -1
+    assert call(ta=110) == -2
+    assert call(tb=114) == -3
+    assert call(M=-1) == -4 and call(N=-1) == -5 and call(K=-1) == -6
+    # row-major: lda >= K (no trans) or M (trans); ldb >= N or K; ldc >= N
+    assert call(lda=K - 1) == -9 and call(ta=T, lda=M - 1) == -9
+    assert call(ldb=N - 1) == -11 and call(tb=T, ldb=K - 1) == -11
+    assert call(ldc=N - 1) == -14
+    # column-major: lda >= M or K; ldb >= K or N; ldc >= M
+    assert call(order=Cm, lda=M - 1) == -9 and call(order=Cm, ta=T, lda=K - 1) == -9
+    assert call(order=Cm, ldb=K - 1) == -11 and call(order=Cm, tb=T, ldb=N - 1) == -11
+    assert call(order=Cm, ldc=M - 1) == -14
+    # strides that are only valid for the other order or flag are accepted where they fit
+    assert call(order=Cm, lda=M, ldb=K, ldc=M, A=None) == -8
+    assert call(path=mm.PATH_FP8_PREQUANTIZED) == -15 and call(path=9) == -15
+    assert call(n=5) == -16
+    assert call(C=None) == -13
+    assert call(A=None) == -8 and call(B=None) == -10
+    nb = mm.gemm_fp8_workspace_bytes(M, N, K)
+    assert call(path=mm.PATH_FP8) == -17
+    assert call(path=mm.PATH_FP8, ws=8, nb=nb) == -17          # unaligned
+    assert call(path=mm.PATH_FP8, ws=256, nb=nb - 1) == -18
+    # empty output: nothing to do, pointers may be NULL
+    assert call(M=0, A=None, B=None, C=None) == 0
+    assert call(order=Cm, N=0, A=None, B=None, C=None) == 0
+    assert mm.gemm_last_error() == ""
+
+
+def test_fp8_workspace_is_symmetric_in_m_and_n():
+    """A column-major FP8 call runs the row-major product with M and N
+    exchanged; the workspace size must not depend on which is which."""
+    import paper_1902_10345_amd as mm
+    for (M, N, K) in [(1, 3000, 7), (4096, 64, 4096), (300, 77, 129)]:
+        assert mm.gemm_fp8_workspace_bytes(M, N, K) == mm.gemm_fp8_workspace_bytes(N, M, K)
