@@ -23,6 +23,10 @@ What it computes (Ben-Nun et al., SC'19):
                           order with transpose flags, as the BLAS-style
                           external-code call of Sec. 2.1 passes them:
                           alpha*op(A)@op(B) + beta*C, op(X) = X or X^T.
+  * ``dgemm``          -- the product for binary64 operands, evaluated in
+                          double-double (compensated dot products, Ogita-Rump-
+                          Oishi "Dot2") and rounded once, so it is far more
+                          accurate than a binary64 result under test.
   * ``norms``          -- relative Frobenius error and componentwise maximum.
 """
 from __future__ import annotations
@@ -83,6 +87,8 @@ def _load():
     lib.orc_fp8_quantize_cols.restype = None
     lib.orc_gemm_fp8_dequant.argtypes = [i64, i64, i64, dbl, vp, vp, vp, vp, dbl, vp, i64, vp, ci]
     lib.orc_gemm_fp8_dequant.restype = None
+    lib.orc_dgemm.argtypes = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, ci, ci]
+    lib.orc_dgemm.restype = None
     lib.orc_norms.argtypes = [i64, i64, vp, i64, vp, vp, vp]
     lib.orc_norms.restype = None
     _lib = lib
@@ -170,6 +176,34 @@ def gemm_op(order, trans_a, trans_b, M, N, K, alpha, A, lda, B, ldb, beta, C, ld
     op_b = np.ascontiguousarray(b.T) if trans_b == TRANS else b
     c0 = stored_matrix(C, order, M, N, ldc) if beta != 0.0 else None
     return gemm(op_a, op_b, alpha=alpha, beta=beta, C0=c0, nthreads=nthreads)
+
+
+def _f64(a):
+    a = np.asarray(a)
+    if a.dtype != np.float64:
+        raise TypeError("oracle expects float64 inputs, got %s" % a.dtype)
+    if a.ndim == 2 and a.size > 0 and a.shape[1] > 1 and a.strides[1] != 8:
+        raise ValueError("rows must be contiguous")
+    return a
+
+
+def dgemm(A, B, alpha=1.0, beta=0.0, C0=None, nthreads=0, absolute=False):
+    """alpha*A@B + beta*C0 for binary64 A, B, C0 in double-double, rounded
+    once (C0 unread when beta == 0); absolute=True gives the componentwise
+    denominator |alpha||A||B| + |beta||C0| instead."""
+    A, B = _f64(A), _f64(B)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    out = np.empty((M, N), dtype=np.float64)
+    c0, ldc0 = None, max(1, N)
+    if beta != 0.0:
+        C0 = _f64(C0)
+        assert C0.shape == (M, N)
+        c0, ldc0 = C0, _ld(C0, N)
+    _load().orc_dgemm(M, N, K, float(alpha), _p(A), _ld(A, K), _p(B), _ld(B, N), float(beta),
+                      _p(c0), ldc0, _p(out), 1 if absolute else 0, int(nthreads))
+    return out
 
 
 def bf16_rne(x: float) -> float:

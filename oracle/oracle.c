@@ -325,3 +325,90 @@ void orc_norms(int64_t M, int64_t N, const float *C, int64_t ldc,
     out[2] = ref;
     out[3] = mx;
 }
+
+/* ------------------------------------------------------------ FP64 GEMM --- */
+
+/* Error-free transformations in binary64 (no fast-math, no contraction):
+ * two_sum: a + b = s + e exactly (Knuth); two_prod: a * b = p + e exactly,
+ * the error term from one fused multiply-add. */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+static void two_prod(double a, double b, double *p, double *e)
+{
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+/* Cref = alpha * A*B + beta*C0 for binary64 operands (the same map-reduce MM,
+ * Sec. 3.3, with the scalars of Sec. 2.1).  Because the result under test is
+ * itself binary64, the reference is evaluated in double-double: each sum over
+ * k is the compensated dot product "Dot2" of Ogita, Rump and Oishi (Accurate
+ * Sum and Dot Product, SIAM J. Sci. Comput. 26(6), 2005) -- every product split
+ * exactly into p + e, p added error-free into the running high part, all
+ * error terms collected in a low part -- and alpha*s + beta*c is formed from
+ * exact products and sums before one final rounding.  Natural k order.
+ * A is MxK (row stride lda), B is KxN (ldb), C0 is MxN (ldc0; unread when
+ * beta == 0); Cref is MxN dense.  absolute != 0 computes the Higham
+ * denominator |alpha||A||B| + |beta||C0| (plain binary64 sums) instead. */
+void orc_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb,
+               double beta, const double *C0, int64_t ldc0, double *Cref,
+               int absolute, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double *lo = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < M; ++i) {
+            double *hi = Cref + i * N;
+            for (int64_t j = 0; j < N; ++j) { hi[j] = 0.0; lo[j] = 0.0; }
+            for (int64_t k = 0; k < K; ++k) {
+                const double a = A[i * lda + k];
+                const double *brow = B + k * ldb;
+                if (absolute) {
+                    for (int64_t j = 0; j < N; ++j) hi[j] += fabs(a) * fabs(brow[j]);
+                    continue;
+                }
+                for (int64_t j = 0; j < N; ++j) {
+                    double p, pe, se;
+                    two_prod(a, brow[j], &p, &pe);
+                    two_sum(hi[j], p, &hi[j], &se);
+                    lo[j] += pe + se;
+                }
+            }
+            for (int64_t j = 0; j < N; ++j) {
+                if (absolute) {
+                    double v = fabs(alpha) * hi[j];
+                    if (beta != 0.0) v += fabs(beta) * fabs(C0[i * ldc0 + j]);
+                    hi[j] = v;
+                    continue;
+                }
+                /* alpha * (hi + lo) as p1 + t */
+                double p1, e1;
+                two_prod(alpha, hi[j], &p1, &e1);
+                double t = e1 + alpha * lo[j];
+                if (beta != 0.0) {
+                    double p2, e2, s, e3;
+                    two_prod(beta, C0[i * ldc0 + j], &p2, &e2);
+                    two_sum(p1, p2, &s, &e3);
+                    hi[j] = s + (t + (e2 + e3));
+                } else {
+                    hi[j] = p1 + t;
+                }
+            }
+        }
+        free(lo);
+    }
+}

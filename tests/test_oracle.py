@@ -439,3 +439,83 @@ def test_gemm_op_beta_zero_never_reads_c():
     got = oracle.gemm_op(oracle.ROW_MAJOR, oracle.NO_TRANS, oracle.NO_TRANS, M, N, K, 1.0,
                          a.reshape(-1), K, b.reshape(-1), N, 0.0, bufC, N)
     assert np.array_equal(got, a.astype(np.float64) @ b.astype(np.float64))
+
+
+# ---- binary64 product (double-double evaluation) ----------------------------
+
+def _exact_int_product(A, B, alpha, beta, C0):
+    M, K = A.shape
+    N = B.shape[1]
+    return [[alpha * sum(int(A[i, k]) * int(B[k, j]) for k in range(K)) +
+             (beta * int(C0[i, j]) if beta else 0) for j in range(N)] for i in range(M)]
+
+
+def test_dgemm_exact_beyond_2_53():
+    """Integer operands up to 2^26: the products reach 2^52 and the sums pass
+    2^53, where binary64 accumulation rounds.  The oracle must return the
+    correctly rounded exact integer (Python ints, float() rounds to nearest
+    even) -- and plain binary64 accumulation must fail, or the case would not
+    test anything."""
+    g = np.random.default_rng(77)
+    M, N, K = 9, 7, 13
+    A = g.integers(-2 ** 26, 2 ** 26, size=(M, K)).astype(np.float64)
+    B = g.integers(-2 ** 26, 2 ** 26, size=(K, N)).astype(np.float64)
+    C0 = g.integers(-2 ** 50, 2 ** 50, size=(M, N)).astype(np.float64)
+    exact = _exact_int_product(A, B, 3, -1, C0)
+    want = np.array([[float(v) for v in row] for row in exact])
+    got = oracle.dgemm(A, B, alpha=3.0, beta=-1.0, C0=C0)
+    assert np.array_equal(got, want)
+    plain = 3.0 * (A @ B) - C0
+    assert not np.array_equal(plain, want)
+
+
+def test_dgemm_matches_exact_rationals():
+    """Random binary64 operands on tiny shapes: the exact rational result
+    (fractions.Fraction), rounded once, against the oracle; the double-double
+    evaluation is faithful, so at most one unit in the last place apart, and
+    equal in all but exceptional near-tie cases."""
+    g = np.random.default_rng(78)
+    exact_hits = total = 0
+    for (M, N, K) in itertools.product((1, 3, 5), (1, 4), (1, 2, 7)):
+        A = g.standard_normal((M, K)) * np.exp2(g.integers(-20, 20, size=(M, K)))
+        B = g.standard_normal((K, N)) * np.exp2(g.integers(-20, 20, size=(K, N)))
+        C0 = g.standard_normal((M, N))
+        got = oracle.dgemm(A, B, alpha=1.25, beta=-0.75, C0=C0)
+        for i in range(M):
+            for j in range(N):
+                r = Fraction(1.25) * sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(K)) \
+                    + Fraction(-0.75) * Fraction(C0[i, j])
+                want = float(r)
+                assert abs(got[i, j] - want) <= np.spacing(abs(want)), (M, N, K, i, j)
+                exact_hits += got[i, j] == want
+                total += 1
+    assert exact_hits >= total - 1
+
+
+def test_dgemm_survives_catastrophic_cancellation():
+    """x + y - x with |x| >> |y|: binary64 accumulation loses y entirely, the
+    compensated sum keeps it (a dropped low part would fail here)."""
+    A = np.array([[1e20, 1.0, -1e20, 3.0]])
+    B = np.array([[1.0], [1.0], [1.0], [1e-30]])
+    got = oracle.dgemm(A, B)
+    assert got[0, 0] == float(Fraction(1) + Fraction(3.0) * Fraction(1e-30))
+    assert (A @ B)[0, 0] != got[0, 0]
+
+
+def test_dgemm_rank_one_closed_form_and_special_cases():
+    K = 4096
+    x = np.arange(1, 6, dtype=np.float64)
+    z = np.arange(-3, 4, dtype=np.float64)
+    kk = np.arange(1, K + 1, dtype=np.float64)
+    A = np.outer(x, kk)
+    B = np.outer(kk, z)
+    got = oracle.dgemm(A, B)
+    closed = np.outer(x, z) * (K * (K + 1) * (2 * K + 1) // 6)
+    assert np.array_equal(got, closed)
+    # beta == 0 never reads C0; alpha == 0 leaves beta*C0
+    C0 = np.full((5, 7), np.nan)
+    assert np.array_equal(oracle.dgemm(A, B, beta=0.0, C0=C0), closed)
+    C1 = np.arange(35, dtype=np.float64).reshape(5, 7)
+    assert np.array_equal(oracle.dgemm(A, B, alpha=0.0, beta=2.0, C0=C1), 2.0 * C1)
+    den = oracle.dgemm(A, B, alpha=-1.0, beta=-2.0, C0=C1, absolute=True)
+    assert np.array_equal(den, np.abs(closed) + 2.0 * C1)
