@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 PEAK_BF16_MFMA = 2516.6
 PEAK_FP8_MFMA = 5033.2
 PEAK_FP32_VALU = 157.3
+PEAK_FP64_MFMA = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -366,6 +367,25 @@ def main():
             lambda: mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, Cf, N),
             flops, PEAK_FP8_MFMA, "fp8_peak")
         del An, Bn, ws, Cf
+        # binary64 on the FP64 matrix cores, and a batched-strided small-matrix
+        # workload (2.0 GFLOP useful: 29 297 products of 32 x 32 x 32)
+        Ad, Bd, Cd = (x.double() for x in (A, B, C))
+        one("f64_4096^3", lambda: mm.gemm_f64(M, N, K, 1.5, Ad, K, Bd, N, 0.5, Cd, N),
+            flops, PEAK_FP64_MFMA, "fp64_peak")
+        del Ad, Bd, Cd
+        ms_, nb_ = 32, 29297
+        gs = torch.Generator(device="cuda").manual_seed(11)
+        Ab = torch.rand(nb_ * ms_ * ms_, device="cuda", dtype=torch.float64, generator=gs)
+        Bb = torch.rand(nb_ * ms_ * ms_, device="cuda", dtype=torch.float64, generator=gs)
+        Cb = torch.rand(nb_ * ms_ * ms_, device="cuda", dtype=torch.float64, generator=gs)
+        sz = ms_ * ms_
+        one("f64_sbsmm_32x32x32_x%d" % nb_,
+            lambda: mm.gemm_f64_strided_batched(ms_, ms_, ms_, 1.0, Ab, ms_, sz, Bb, ms_, sz, 0.0,
+                                                Cb, ms_, sz, nb_),
+            2.0 * ms_ ** 3 * nb_, PEAK_FP64_MFMA, "fp64_peak")
+        paths["f64_sbsmm_32x32x32_x%d" % nb_]["hbm_gbs"] = round(
+            3 * 8 * sz * nb_ / (paths["f64_sbsmm_32x32x32_x%d" % nb_]["ms"] * 1e-3) / 1e9, 1)
+        del Ab, Bb, Cb
         M2, N2, K2 = 8192, 2048, 4096
         _, (A2, B2, C2) = _dev_inputs(M2, N2, K2, 3, torch)
         fl2 = 2.0 * M2 * N2 * K2

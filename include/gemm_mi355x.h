@@ -161,6 +161,42 @@ gemm_status gemm_fp8_prequantized(int64_t M, int64_t N, int64_t K, float alpha,
 gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Binary64 path on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+ * C <- alpha*A*B + beta*C with binary64 operands, products and sums, for the
+ * double-precision workloads the paper evaluates (the Polybench kernels run
+ * mostly in double precision, Sec. 6.1; the batched-strided small products of
+ * the quantum-transport case study, Sec. 6.4 and table "Strided Matrix
+ * Multiplication Performance", are double precision by the peak they are
+ * measured against).  Layout, quick returns, status codes and determinism as
+ * gemm_f32.  Arguments: 1 M, 2 N, 3 K, 4 alpha, 5 A, 6 lda, 7 B, 8 ldb,
+ * 9 beta, 10 C, 11 ldc, 12 stream.
+ * ---------------------------------------------------------------------- */
+gemm_status gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
+                     const double *A, int64_t lda, const double *B, int64_t ldb,
+                     double beta, double *C, int64_t ldc, hipStream_t stream);
+
+/* Batched-strided binary64 product (SBSMM, Sec. 6.4): `batch` independent
+ * problems of one shape, problem b reading A + b*stride_a, B + b*stride_b and
+ * updating C + b*stride_c (strides in elements; a zero input stride reuses
+ * one matrix for every problem).  Output matrices must not overlap:
+ * stride_c >= (M-1)*ldc + N when batch > 1.  One launch covers up to 65535
+ * problems (more are issued as consecutive launches on the stream).
+ * Arguments: 1 M, 2 N, 3 K, 4 alpha, 5 A, 6 lda, 7 stride_a, 8 B, 9 ldb,
+ * 10 stride_b, 11 beta, 12 C, 13 ldc, 14 stride_c, 15 batch, 16 stream. */
+gemm_status gemm_f64_strided_batched(int64_t M, int64_t N, int64_t K, double alpha,
+                                     const double *A, int64_t lda, int64_t stride_a,
+                                     const double *B, int64_t ldb, int64_t stride_b,
+                                     double beta, double *C, int64_t ldc, int64_t stride_c,
+                                     int64_t batch, hipStream_t stream);
+
+/* gemm_f64 with an explicit tile configuration of GEMM_PATH_F64 (0 <= cfg <
+ * gemm_num_configs(GEMM_PATH_F64), or -1 for the default).  Arguments: 1 cfg,
+ * then 2..13 as gemm_f64's 1..12. */
+gemm_status gemm_f64_run_config(int cfg, int64_t M, int64_t N, int64_t K, double alpha,
+                                const double *A, int64_t lda, const double *B, int64_t ldb,
+                                double beta, double *C, int64_t ldc, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Tile configurations (for the autotuner and for per-configuration tests).
  * Every configuration of a path computes the same operation; results may
  * differ between configurations only by binary32 summation order.
@@ -178,6 +214,8 @@ gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream
 #define GEMM_PATH_3XBF16  1
 #define GEMM_PATH_FP8     2
 #define GEMM_PATH_FP8_PREQUANTIZED 3
+#define GEMM_PATH_F64     4  /* configurations only (gemm_num_configs, gemm_config_name,
+                                gemm_default_config); run with gemm_f64_run_config */
 int gemm_num_configs(int path);
 const char *gemm_config_name(int path, int cfg);
 /* Default configuration the library picks for this shape on the current device. */

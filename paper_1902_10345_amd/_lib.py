@@ -72,6 +72,11 @@ _sig("gemm_fp8_scaled", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32
 _sig("fp8_quantize", _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
 _sig("gemm_fp8_prequantized", _int, _i64, _i64, _i64, _f32, _vp, _sz, _f32, _vp, _i64, _vp)
 _sig("fp8_e4m3_encode", _int, _i64, _vp, _vp, _vp)
+_sig("gemm_f64", _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _vp)
+_sig("gemm_f64_run_config", _int, _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp,
+     _i64, _vp)
+_sig("gemm_f64_strided_batched", _int, _i64, _i64, _i64, _dbl, _vp, _i64, _i64, _vp, _i64, _i64,
+     _dbl, _vp, _i64, _i64, _i64, _vp)
 _sig("gemm_ex", _int, _int, _int, _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp,
      _i64, _int, _int, _vp, _sz, _vp)
 
@@ -221,7 +226,24 @@ def fp8_workspace_layout(M, N, K):
     return {"Kp": Kp, "qa": qa, "qb": qb, "sa": sa, "sb": sb}
 
 
-PATH_F32, PATH_3XBF16, PATH_FP8, PATH_FP8_PREQUANTIZED = 0, 1, 2, 3
+PATH_F32, PATH_3XBF16, PATH_FP8, PATH_FP8_PREQUANTIZED, PATH_F64 = 0, 1, 2, 3, 4
+
+
+def gemm_f64(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    return check(lib.gemm_f64(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
+                              stream_handle(stream)))
+
+
+def gemm_f64_run_config(cfg, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    return check(lib.gemm_f64_run_config(cfg, M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta,
+                                         ptr(C), ldc, stream_handle(stream)))
+
+
+def gemm_f64_strided_batched(M, N, K, alpha, A, lda, stride_a, B, ldb, stride_b, beta, C, ldc,
+                             stride_c, batch, stream=None):
+    return check(lib.gemm_f64_strided_batched(M, N, K, alpha, ptr(A), lda, stride_a, ptr(B), ldb,
+                                              stride_b, beta, ptr(C), ldc, stride_c, batch,
+                                              stream_handle(stream)))
 ROW_MAJOR, COL_MAJOR = 101, 102
 NO_TRANS, TRANS, CONJ_TRANS = 111, 112, 113
 

@@ -4,6 +4,7 @@
 // compilation pipeline (Sec. 4.3): nothing is enqueued until every argument
 // has been checked.  Argument rules follow the BLAS-style call of the paper's
 // external-code example (Sec. 2.1), read as row-major with no transposes.
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -58,9 +59,10 @@ struct Checked {
   bool scale_only = false;  // alpha == 0 or K == 0
 };
 
-static gemm_status check_gemm_args(const char *fn, int64_t M, int64_t N, int64_t K, float alpha,
-                                   const float *A, int64_t lda, const float *B, int64_t ldb,
-                                   const float *C, int64_t ldc, Checked &ck) {
+template <typename T>
+static gemm_status check_gemm_args(const char *fn, int64_t M, int64_t N, int64_t K, T alpha,
+                                   const T *A, int64_t lda, const T *B, int64_t ldb,
+                                   const T *C, int64_t ldc, Checked &ck) {
   if (M < 0) return bad_arg(1, fn, "(M) must be >= 0");
   if (N < 0) return bad_arg(2, fn, "(N) must be >= 0");
   if (K < 0) return bad_arg(3, fn, "(K) must be >= 0");
@@ -71,7 +73,7 @@ static gemm_status check_gemm_args(const char *fn, int64_t M, int64_t N, int64_t
   if (ldc < (N > 1 ? N : 1)) return bad_arg(11, fn, "(ldc) must be >= max(1,N)");
   if (M == 0 || N == 0) { ck.noop = true; return GEMM_STATUS_OK; }
   if (!C) return bad_arg(10, fn, "(C) is NULL");
-  if (alpha == 0.0f || K == 0) { ck.scale_only = true; return GEMM_STATUS_OK; }
+  if (alpha == (T)0 || K == 0) { ck.scale_only = true; return GEMM_STATUS_OK; }
   if (!A) return bad_arg(5, fn, "(A) is NULL");
   if (!B) return bad_arg(7, fn, "(B) is NULL");
   return GEMM_STATUS_OK;
@@ -248,6 +250,7 @@ gemm_status fp8_e4m3_encode(int64_t n, const float *x, uint8_t *codes, hipStream
 
 int gemm_num_configs(int path) {
   switch (path) {
+    case GEMM_PATH_F64: return f64_num_configs();
     case GEMM_PATH_F32: return f32_num_configs();
     case GEMM_PATH_3XBF16: return bx3_num_configs();
     case GEMM_PATH_FP8:
@@ -263,11 +266,13 @@ const char *gemm_config_name(int path, int cfg) {
     case GEMM_PATH_3XBF16: return bx3_config(cfg).name;
     case GEMM_PATH_FP8:
     case GEMM_PATH_FP8_PREQUANTIZED: return fp8_config_name(cfg);
+    case GEMM_PATH_F64: return f64_config(cfg).name;
     default: return "";
   }
 }
 
 int gemm_default_config(int path, int64_t M, int64_t N, int64_t K) {
+  if (path == GEMM_PATH_F64) return f64_default_config(M, N, K, 1);
   if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8_PREQUANTIZED) return -1;
   return pick_config(path, 3, M, N, K);
 }
@@ -279,6 +284,7 @@ gemm_status gemm_run_config(int path, int cfg, int64_t M, int64_t N, int64_t K, 
   clear_error();
   const char *fn = "gemm_run_config";
   if (gemm_num_configs(path) == 0) return bad_arg(1, fn, "(path) unknown or not built");
+  if (path == GEMM_PATH_F64) return bad_arg(1, fn, "(path) binary64 operands go through gemm_f64_run_config");
   if (cfg < -1 || cfg >= gemm_num_configs(path)) return bad_arg(2, fn, "(cfg) out of range");
   if (path == GEMM_PATH_FP8_PREQUANTIZED) {  // operands are the workspace's codes
     if (M < 0) return bad_arg(3, fn, "(M) must be >= 0");
@@ -385,6 +391,80 @@ gemm_status gemm_ex(int order, int trans_a, int trans_b, int64_t M, int64_t N, i
   const int cfg = trans ? bx3_default_config(g.M, g.N, K, n_products)
                         : pick_config(GEMM_PATH_3XBF16, n_products, g.M, g.N, K);
   return bx3_run(g, cfg, stream);
+}
+
+gemm_status gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                     int64_t lda, const double *B, int64_t ldb, double beta, double *C,
+                     int64_t ldc, hipStream_t stream) {
+  clear_error();
+  Checked ck;
+  gemm_status st = check_gemm_args("gemm_f64", M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st || ck.noop) return st;
+  if (ck.scale_only) return scale_c_f64(M, N, beta, C, ldc, 0, 1, stream);
+  GemmArgsF64 g{M, N, K, alpha, beta, A, lda, 0, B, ldb, 0, C, ldc, 0, 1};
+  return f64_run(g, f64_default_config(M, N, K, 1), stream);
+}
+
+gemm_status gemm_f64_run_config(int cfg, int64_t M, int64_t N, int64_t K, double alpha,
+                                const double *A, int64_t lda, const double *B, int64_t ldb,
+                                double beta, double *C, int64_t ldc, hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_f64_run_config";
+  if (cfg < -1 || cfg >= f64_num_configs()) return bad_arg(1, fn, "(cfg) out of range");
+  Checked ck;
+  gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  if (st < 0) {  // argument index shifted by cfg
+    set_error(std::string(fn) + ": argument " + std::to_string(1 - st) + " invalid");
+    return st - 1;
+  }
+  if (ck.noop) return GEMM_STATUS_OK;
+  if (ck.scale_only) return scale_c_f64(M, N, beta, C, ldc, 0, 1, stream);
+  GemmArgsF64 g{M, N, K, alpha, beta, A, lda, 0, B, ldb, 0, C, ldc, 0, 1};
+  return f64_run(g, cfg < 0 ? f64_default_config(M, N, K, 1) : cfg, stream);
+}
+
+gemm_status gemm_f64_strided_batched(int64_t M, int64_t N, int64_t K, double alpha,
+                                     const double *A, int64_t lda, int64_t stride_a,
+                                     const double *B, int64_t ldb, int64_t stride_b, double beta,
+                                     double *C, int64_t ldc, int64_t stride_c, int64_t batch,
+                                     hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_f64_strided_batched";
+  if (M < 0) return bad_arg(1, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(2, fn, "(N) must be >= 0");
+  if (K < 0) return bad_arg(3, fn, "(K) must be >= 0");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL)
+    return bad_arg(M > 0x7fffffffLL ? 1 : N > 0x7fffffffLL ? 2 : 3, fn, "exceeds 2^31-1");
+  if (lda < (K > 1 ? K : 1)) return bad_arg(6, fn, "(lda) must be >= max(1,K)");
+  if (stride_a < 0) return bad_arg(7, fn, "(stride_a) must be >= 0");
+  if (ldb < (N > 1 ? N : 1)) return bad_arg(9, fn, "(ldb) must be >= max(1,N)");
+  if (stride_b < 0) return bad_arg(10, fn, "(stride_b) must be >= 0");
+  if (ldc < (N > 1 ? N : 1)) return bad_arg(13, fn, "(ldc) must be >= max(1,N)");
+  if (batch < 0) return bad_arg(15, fn, "(batch) must be >= 0");
+  // outputs of different problems must not overlap (they are written concurrently)
+  if (batch > 1 && M > 0 && N > 0 && stride_c < (M - 1) * ldc + N)
+    return bad_arg(14, fn, "(stride_c) smaller than one output matrix");
+  if (M == 0 || N == 0 || batch == 0) return GEMM_STATUS_OK;
+  if (!C) return bad_arg(12, fn, "(C) is NULL");
+  if (alpha == 0.0 || K == 0) {
+    for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+      const int64_t nb = std::min<int64_t>(65535, batch - b0);
+      if (gemm_status st = scale_c_f64(M, N, beta, C + b0 * stride_c, ldc, stride_c, nb, stream))
+        return st;
+    }
+    return GEMM_STATUS_OK;
+  }
+  if (!A) return bad_arg(5, fn, "(A) is NULL");
+  if (!B) return bad_arg(8, fn, "(B) is NULL");
+  const int cfg = f64_default_config(M, N, K, batch);
+  // the grid's second dimension holds at most 65535 problems per launch
+  for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+    const int64_t nb = std::min<int64_t>(65535, batch - b0);
+    GemmArgsF64 g{M, N, K, alpha, beta, A + b0 * stride_a, lda, stride_a, B + b0 * stride_b, ldb,
+                  stride_b, C + b0 * stride_c, ldc, stride_c, nb};
+    if (gemm_status st = f64_run(g, cfg, stream)) return st;
+  }
+  return GEMM_STATUS_OK;
 }
 
 size_t err_norm_workspace_bytes(void) { return errnorm_ws_bytes(); }

@@ -53,6 +53,25 @@ gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
                       hipStream_t s);
 
+// Binary64 path (single problem: batch 1, strides unused).
+struct GemmArgsF64 {
+  int64_t M, N, K;
+  double alpha, beta;
+  const double *A;
+  int64_t lda, sa;
+  const double *B;
+  int64_t ldb, sb;
+  double *C;
+  int64_t ldc, sc;
+  int64_t batch;
+};
+int f64_num_configs();
+const TileConfig &f64_config(int i);
+int f64_default_config(int64_t M, int64_t N, int64_t K, int64_t batch);
+gemm_status f64_run(const GemmArgsF64 &g, int cfg, hipStream_t s);
+gemm_status scale_c_f64(int64_t M, int64_t N, double beta, double *C, int64_t ldc, int64_t sc,
+                        int64_t batch, hipStream_t s);
+
 // Scaled FP8 path.
 size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K);
 int64_t fp8_kp(int64_t K);

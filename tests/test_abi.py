@@ -98,7 +98,7 @@ def test_configs_have_names():
     assert [mm.gemm_config_name(mm.PATH_FP8, i) for i in range(mm.gemm_num_configs(mm.PATH_FP8))] == \
         [mm.gemm_config_name(mm.PATH_FP8_PREQUANTIZED, i)
          for i in range(mm.gemm_num_configs(mm.PATH_FP8_PREQUANTIZED))]
-    assert mm.gemm_num_configs(4) == 0 and mm.gemm_config_name(4, 0) == ""
+    assert mm.gemm_num_configs(5) == 0 and mm.gemm_config_name(5, 0) == ""
 
 
 def test_prequantized_run_config_argument_codes():

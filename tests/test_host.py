@@ -245,3 +245,41 @@ def test_fp8_workspace_is_symmetric_in_m_and_n():
     import paper_1902_10345_amd as mm
     for (M, N, K) in [(1, 3000, 7), (4096, 64, 4096), (300, 77, 129)]:
         assert mm.gemm_fp8_workspace_bytes(M, N, K) == mm.gemm_fp8_workspace_bytes(N, M, K)
+
+
+def test_f64_argument_codes_and_configs():
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    assert mm.gemm_num_configs(mm.PATH_F64) >= 2
+    names = [mm.gemm_config_name(mm.PATH_F64, c) for c in range(mm.gemm_num_configs(mm.PATH_F64))]
+    assert all(n.startswith("f64_") for n in names) and len(set(names)) == len(names)
+    assert 0 <= mm.gemm_default_config(mm.PATH_F64, 4096, 4096, 4096) < len(names)
+    assert lib.gemm_f64(-1, 4, 4, 1.0, F, 4, F, 4, 0.0, F, 4, None) == -1
+    assert lib.gemm_f64(4, 4, 4, 1.0, F, 3, F, 4, 0.0, F, 4, None) == -6
+    assert lib.gemm_f64(4, 4, 4, 1.0, F, 4, F, 3, 0.0, F, 4, None) == -8
+    assert lib.gemm_f64(4, 4, 4, 1.0, F, 4, F, 4, 0.0, F, 3, None) == -11
+    assert lib.gemm_f64(4, 4, 4, 1.0, None, 4, F, 4, 0.0, F, 4, None) == -5
+    assert lib.gemm_f64(4, 4, 4, 1.0, F, 4, None, 4, 0.0, F, 4, None) == -7
+    assert lib.gemm_f64(4, 4, 4, 1.0, F, 4, F, 4, 0.0, None, 4, None) == -10
+    assert lib.gemm_f64(0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, None) == 0
+    assert lib.gemm_f64_run_config(99, 4, 4, 4, 1.0, F, 4, F, 4, 0.0, F, 4, None) == -1
+    assert lib.gemm_f64_run_config(0, 4, 4, 4, 1.0, F, 3, F, 4, 0.0, F, 4, None) == -7
+    # the binary32 per-configuration entry point refuses binary64 operands
+    assert lib.gemm_run_config(mm.PATH_F64, 0, 4, 4, 4, 1.0, F, 4, F, 4, 0.0, F, 4, 3, None, 0,
+                               None) == -1
+    sb = lib.gemm_f64_strided_batched
+    args = lambda **kw: [kw.get(k, v) for k, v in (  # noqa: E731
+        ("M", 4), ("N", 4), ("K", 4), ("alpha", 1.0), ("A", F), ("lda", 4), ("sa", 16), ("B", F),
+        ("ldb", 4), ("sb", 16), ("beta", 0.0), ("C", F), ("ldc", 4), ("sc", 16), ("batch", 3))] + [None]
+    assert sb(*args(M=-1)) == -1
+    assert sb(*args(lda=3)) == -6
+    assert sb(*args(sa=-1)) == -7
+    assert sb(*args(ldb=3)) == -9
+    assert sb(*args(sb=-4)) == -10
+    assert sb(*args(ldc=3)) == -13
+    assert sb(*args(sc=15)) == -14          # outputs would overlap
+    assert sb(*args(batch=-1)) == -15
+    assert sb(*args(C=None)) == -12
+    assert sb(*args(A=None)) == -5 and sb(*args(B=None)) == -8
+    assert sb(*args(batch=0, A=None, B=None, C=None)) == 0
+    assert sb(*args(sc=0, batch=1, A=None)) == -5   # one problem: any output stride
