@@ -297,6 +297,127 @@ gemm_status launch(const GemmArgsF64 &g, hipStream_t s) {
   return check_launch("gemm_f64_kernel");
 }
 
+// Batched small problems (M, N <= 16 SB): one wave per problem, four
+// problems per workgroup, operands loaded from memory straight into MFMA
+// fragments (each element is used by one wave only, so staging through LDS
+// would only add traffic).  The k range is walked in chunks of 16: lane group
+// g takes four k of every block (two 128-bit loads of an A row when the
+// chunk lies inside [0, K) and lda is even, else four 64-bit loads) and the
+// four B values of its column at those k (64-bit loads, consecutive lanes on
+// consecutive columns); MFMA step q multiplies the group's q-th k.
+// Rows past M and columns past N read zero through the buffer range check;
+// k past K is masked per element.
+template <int SB, bool VEC, bool BETA>
+__global__ __launch_bounds__(256, 2) void small_batched_kernel(
+    int M, int N, int K, double alpha, const double *__restrict__ A, int64_t lda, int64_t sa,
+    const double *__restrict__ B, int64_t ldb, int64_t sb, double beta, double *__restrict__ C,
+    int64_t ldc, int64_t sc, int64_t batch) {
+  const int lane = threadIdx.x & 63;
+  // the wave index is uniform across the wave; saying so keeps the problem's
+  // buffer resources in scalar registers (no per-lane resource loops)
+  const int64_t prob = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (prob >= batch) return;
+  const int lr = lane & 15, lg = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rA = rsrc(A + prob * sa, ((int64_t)(M - 1) * lda + K) * 8);
+  const __amdgpu_buffer_rsrc_t rB = rsrc(B + prob * sb, ((int64_t)(K - 1) * ldb + N) * 8);
+  double *Cp = C + prob * sc;
+  // column offsets of this lane's B blocks; columns past N read zero
+  int bcol[SB];
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    const int n = 16 * j + lr;
+    bcol[j] = n < N ? n * 8 : (int)0x80000000;
+  }
+  int arow[SB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    const int r = 16 * i + lr;
+    arow[i] = r < M ? r * (int)lda * 8 : (int)0x80000000;
+  }
+  f64x4 acc[SB][SB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    // lane group g takes k = k0 + 2g, +1 (q = 0, 1) and k0 + 8 + 2g, +1
+    // (q = 2, 3): one 128-bit load of the four groups reads 64 contiguous
+    // bytes of each A row
+    auto kq = [&](int q) { return k0 + 2 * lg + (q & 1) + 8 * (q >> 1); };
+    double a[SB][4], b[SB][4];
+    if (k0 + 16 <= K) {
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        if (VEC) {
+          const f64x2 v0 = ld2(rA, arow[i] + kq(0) * 8), v1 = ld2(rA, arow[i] + kq(2) * 8);
+          a[i][0] = v0.x; a[i][1] = v0.y; a[i][2] = v1.x; a[i][3] = v1.y;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[i][q] = ld1(rA, arow[i] + kq(q) * 8, 0);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < SB; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[j][q] = ld1(rB, bcol[j] + kq(q) * (int)ldb * 8, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool kin = kq(q) < K;
+#pragma unroll
+        for (int i = 0; i < SB; ++i) a[i][q] = ld1(rA, kin ? arow[i] + kq(q) * 8 : (int)0x80000000, 0);
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+          b[j][q] = ld1(rB, kin ? bcol[j] + kq(q) * (int)ldb * 8 : (int)0x80000000, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < SB; ++i)
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      const int col = 16 * j + lr;
+      if (col >= N) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 16 * i + lg + 4 * e;
+        if (row < M) {
+          double *p = Cp + (int64_t)row * ldc + col;
+          const double v = alpha * acc[i][j][e];
+          *p = BETA ? fma(beta, *p, v) : v;
+        }
+      }
+    }
+}
+
+template <int SB>
+gemm_status launch_small(const GemmArgsF64 &g, hipStream_t s) {
+  if (((int64_t)(16 * SB) * g.lda + g.K) * 8 >= ((int64_t)1 << 31) ||
+      ((int64_t)g.K * g.ldb + g.N) * 8 >= ((int64_t)1 << 31)) {
+    set_error("gemm_f64: lda or ldb too large for 32-bit offsets of the small-problem kernel");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  const bool vec = g.lda % 2 == 0 && g.sa % 2 == 0 && ((uintptr_t)g.A & 15) == 0;
+  const bool beta = g.beta != 0.0;
+  const int64_t nwg = (g.batch + 3) / 4;
+  if (nwg > 0x7fffffff) { set_error("gemm_f64: batch too large"); return GEMM_STATUS_UNSUPPORTED; }
+#define MM_LAUNCH(V, BT)                                                                            \
+  hipLaunchKernelGGL((small_batched_kernel<SB, V, BT>), dim3((unsigned)nwg), dim3(256), 0, s,       \
+                     (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.sa, g.B, g.ldb, g.sb,     \
+                     g.beta, g.C, g.ldc, g.sc, g.batch)
+  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
+  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
+#undef MM_LAUNCH
+  return check_launch("small_batched_kernel");
+}
+
 // C <- beta*C over a batch (alpha == 0 or K == 0).
 template <bool BETA>
 __global__ __launch_bounds__(256) void scale_kernel(int64_t M, int64_t N, double beta,
@@ -321,6 +442,10 @@ static const F64Config kF64Configs[] = {
     {{128, 128, 16, "f64_128x128x16_4w64x64"}},
     {{256, 128, 16, "f64_256x128x16_8w64x64"}},
     {{64, 64, 16, "f64_64x64x16_4w32x32"}},
+    // one wave per problem, operands straight into MFMA fragments (M, N <= 16 / 32 / 64)
+    {{16, 16, 16, "f64_small_16"}},
+    {{32, 32, 16, "f64_small_32"}},
+    {{64, 64, 16, "f64_small_64"}},
 };
 
 int f64_num_configs() { return (int)(sizeof(kF64Configs) / sizeof(kF64Configs[0])); }
@@ -330,6 +455,8 @@ int f64_default_config(int64_t M, int64_t N, int64_t K, int64_t batch) {
   (void)K;
   const int64_t cus = num_cus();
   auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch; };
+  // batches of small problems: one wave per problem
+  if (batch > 1 && M <= 64 && N <= 64) return M <= 16 && N <= 16 ? 3 : (M <= 32 && N <= 32 ? 4 : 5);
   // 64 x 64 tiles for problems that would fill little of a 128 x 128 tile,
   // or whose 128 x 128 tiles leave compute units idle
   if (M <= 64 || N <= 64) return 2;
@@ -342,6 +469,17 @@ gemm_status f64_run(const GemmArgsF64 &g, int cfg, hipStream_t s) {
     case 0: return f64::launch<128, 128, 64, 64>(g, s);
     case 1: return f64::launch<256, 128, 64, 64>(g, s);
     case 2: return f64::launch<64, 64, 32, 32>(g, s);
+    case 3:
+    case 4:
+    case 5: {
+      const int lim = cfg == 3 ? 16 : cfg == 4 ? 32 : 64;
+      if (g.M > lim || g.N > lim) {
+        set_error("gemm_f64: problem larger than the small-problem configuration");
+        return GEMM_STATUS_UNSUPPORTED;
+      }
+      return cfg == 3 ? f64::launch_small<1>(g, s)
+                      : cfg == 4 ? f64::launch_small<2>(g, s) : f64::launch_small<4>(g, s);
+    }
     default: set_error("gemm_f64: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

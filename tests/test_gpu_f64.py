@@ -76,13 +76,32 @@ def test_parity_default_config(M, N, K, alpha, beta):
     _check(A, B, C0, C, alpha, beta)
 
 
-@pytest.mark.parametrize("M,N,K", [(300, 260, 333), (129, 67, 1001), (256, 128, 48)])
+def _fits(mm, cfg, M, N):
+    name = mm.gemm_config_name(mm.PATH_F64, cfg)
+    if not name.startswith("f64_small_"):
+        return True
+    lim = int(name.rsplit("_", 1)[1])
+    return M <= lim and N <= lim
+
+
+@pytest.mark.parametrize("M,N,K", [(300, 260, 333), (129, 67, 1001), (256, 128, 48), (16, 16, 40),
+                                   (13, 7, 33), (32, 32, 32), (29, 31, 17), (64, 64, 100),
+                                   (50, 3, 64), (1, 1, 1)])
 def test_every_config(M, N, K):
+    """Every configuration that accepts the shape (the small-problem ones take
+    M, N up to their size and refuse larger problems)."""
     import paper_1902_10345_amd as mm
     A, B, C0 = _u((M, K), 3), _u((K, N), 4), _u((M, N), 5)
+    ran = 0
     for cfg in range(mm.gemm_num_configs(mm.PATH_F64)):
+        if not _fits(mm, cfg, M, N):
+            with pytest.raises(mm.GemmError):
+                _run(mm, A, B, C0, 1.5, 0.5, cfg=cfg)
+            continue
         _, C = _run(mm, A, B, C0, 1.5, 0.5, cfg=cfg)
         _check(A, B, C0, C, 1.5, 0.5)
+        ran += 1
+    assert ran >= 3
 
 
 def test_every_config_integer_inputs_are_exact():
@@ -93,8 +112,19 @@ def test_every_config_integer_inputs_are_exact():
     C0 = si.integers((M, N), 9, -1000, 1000).astype(np.float64)
     exact = oracle.dgemm(A, B, alpha=2.0, beta=-3.0, C0=C0)
     for cfg in range(mm.gemm_num_configs(mm.PATH_F64)):
+        if not _fits(mm, cfg, M, N):
+            continue
         _, C = _run(mm, A, B, C0, 2.0, -3.0, cfg=cfg)
         assert np.array_equal(C, exact), mm.gemm_config_name(mm.PATH_F64, cfg)
+    # and the small-problem configurations on a shape they take
+    A2, B2, C2 = A[:64, :77], B[:77, :64], C0[:64, :64]
+    exact2 = oracle.dgemm(np.ascontiguousarray(A2), np.ascontiguousarray(B2), alpha=2.0, beta=-3.0,
+                          C0=np.ascontiguousarray(C2))
+    for cfg in range(mm.gemm_num_configs(mm.PATH_F64)):
+        if _fits(mm, cfg, 64, 64):
+            _, C = _run(mm, np.ascontiguousarray(A2), np.ascontiguousarray(B2),
+                        np.ascontiguousarray(C2), 2.0, -3.0, cfg=cfg)
+            assert np.array_equal(C, exact2), mm.gemm_config_name(mm.PATH_F64, cfg)
 
 
 def test_padded_odd_leading_dimensions_and_untouched_padding():
@@ -185,7 +215,9 @@ def _batched(mm, M, N, K, batch, seed, pad=(0, 0, 0), share_b=False, alpha=1.5, 
 
 
 @pytest.mark.parametrize("M,N,K,batch", [(16, 16, 16, 100), (32, 32, 32, 37), (12, 12, 12, 50),
-                                         (70, 50, 90, 9), (130, 129, 64, 3), (1, 1, 5, 7)])
+                                         (70, 50, 90, 9), (130, 129, 64, 3), (1, 1, 5, 7),
+                                         (64, 64, 64, 11), (33, 17, 40, 13), (64, 40, 7, 6),
+                                         (16, 32, 100, 21)])
 def test_batched_strided_parity(M, N, K, batch):
     import paper_1902_10345_amd as mm
     _batched(mm, M, N, K, batch, M + N + K + batch)
