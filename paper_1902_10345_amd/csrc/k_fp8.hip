@@ -663,11 +663,13 @@ static gemm_status fp8_launch(int64_t M, int64_t N, const fp8::Layout &L, float 
   return check_launch("gemm_fp8_kernel");
 }
 
-int fp8_num_configs() { return 3; }
+int fp8_num_configs() { return 5; }
 const char *fp8_config_name(int cfg) {
   switch (cfg) {
     case 0: return "fp8_256x256x128_8w128x64";
     case 1: return "fp8_256x256x128_4w128x128";
+    case 3: return "fp8_128x128x128_4w64x64_dma";
+    case 4: return "fp8_256x128x128_8w64x64_dma";
     default: return "fp8_256x256x128_8w128x64_dma";
   }
 }
@@ -678,11 +680,18 @@ gemm_status fp8_gemm_run_cfg(int64_t M, int64_t N, int64_t K, float alpha, const
   const uint8_t *base = static_cast<const uint8_t *>(ws);
   if (cfg == 1) return fp8_launch<256, 256, 128, 128, false>(M, N, L, alpha, base, beta, C, ldc, s);
   if (cfg == 2) return fp8_launch<256, 256, 128, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
+  if (cfg == 3) return fp8_launch<128, 128, 64, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
+  if (cfg == 4) return fp8_launch<256, 128, 64, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
   return fp8_launch<256, 256, 128, 64, false>(M, N, L, alpha, base, beta, C, ldc, s);
 }
 
-// The direct-to-LDS kernel is the fastest at every measured shape.
-int fp8_default_config(int64_t, int64_t, int64_t) { return 2; }
+// Direct-to-LDS kernels: 256 x 256 tiles while they fill every compute unit
+// (measured best at 4096^3 and above), 128 x 128 tiles -- two workgroups per
+// compute unit -- below that (1.9x at 2048^3 and at 1024 x 4096 x 4096).
+int fp8_default_config(int64_t M, int64_t N, int64_t) {
+  const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
+  return big >= num_cus() ? 2 : 3;
+}
 
 gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s) {
   const int64_t want = (n + 255) / 256;
