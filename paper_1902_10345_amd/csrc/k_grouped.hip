@@ -66,16 +66,22 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const Desc *__restrict_
   const bool in_lds = count < kLdsStarts;
   if (in_lds)
     for (int i = threadIdx.x; i <= count; i += 256) s_starts[i] = starts[i];
-  // Tiles [0, static_tiles) are dealt round-robin (tile t to workgroup t mod
-  // G): the list is sorted longest first, so each round hands every
+  // Tiles [0, static_tiles) are dealt round-robin (tile t to slot t mod G):
+  // the list is sorted longest first, so each round hands every
   // workgroup a tile of similar cost and needs no atomics.  The remaining
   // tiles are dequeued from the counter (first come, first served), which
   // evens out the tail; a whole grid's worth of simultaneous same-address
   // atomics would otherwise serialise at the start of every launch.
+  // Workgroup ids are dispatched round robin over the 8 XCDs; the slot
+  // permutation hands each XCD a run of G/8 consecutive tiles per round, so
+  // neighbouring tiles of a problem -- which share A row panels and B column
+  // panels -- run on one XCD and meet in its L2 instead of being fetched from
+  // HBM once per XCD.
   const int G = gridDim.x;
+  const int w = (int)blockIdx.x;
+  const int slot = G % 8 == 0 ? (w % 8) * (G / 8) + w / 8 : w;
   if (threadIdx.x == 0)
-    s_tile[0] = (int)blockIdx.x < static_tiles ? (int)blockIdx.x
-                                               : static_tiles + (int)atomicAdd(counter, 1u);
+    s_tile[0] = slot < static_tiles ? slot : static_tiles + (int)atomicAdd(counter, 1u);
   __syncthreads();
   // Values read from LDS are per-lane to the compiler; the tile index is
   // wave-uniform by construction, and saying so keeps everything derived
