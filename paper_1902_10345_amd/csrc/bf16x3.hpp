@@ -39,16 +39,22 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // num_records.
 constexpr int kBufferFlags = 0x00020000;
 
-// Round-to-nearest-even split of a binary32 value into bfloat16 planes.
-__device__ __forceinline__ void split2(float x, __bf16 &h, __bf16 &l) {
-  h = (__bf16)x;
-  l = (__bf16)(x - (float)h);
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Round-to-nearest-even split of binary32 values into bfloat16 planes, two
+// values at a time: v_cvt_pk_bf16_f32 rounds a pair in one instruction, and
+// widening a bfloat16 back to binary32 is exact, so x - h is the exact
+// remainder.
+__device__ __forceinline__ void split2(f32x2 x, bf16x2 &h, bf16x2 &l) {
+  h = __builtin_convertvector(x, bf16x2);
+  l = __builtin_convertvector(x - __builtin_convertvector(h, f32x2), bf16x2);
 }
-__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
-  h = (__bf16)x;
-  const float r = x - (float)h;
-  m = (__bf16)r;
-  l = (__bf16)(r - (float)m);
+__device__ __forceinline__ void split3(f32x2 x, bf16x2 &h, bf16x2 &m, bf16x2 &l) {
+  h = __builtin_convertvector(x, bf16x2);
+  const f32x2 r = x - __builtin_convertvector(h, f32x2);
+  m = __builtin_convertvector(r, bf16x2);
+  l = __builtin_convertvector(r - __builtin_convertvector(m, f32x2), bf16x2);
 }
 
 // XOR swizzle of the 16-byte chunk index of an LDS row holding BK bf16.
@@ -267,13 +273,13 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   // ---- split + registers -> LDS --------------------------------------------
   auto split8 = [&](const float (&x)[8], bf16x8 &h, bf16x8 &m, bf16x8 &l) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      __bf16 x0, x1, x2;
-      if constexpr (NP == 2) split2(x[e], x0, x1);
-      else split3(x[e], x0, x1, x2);
-      h[e] = x0;
-      m[e] = x1;
-      if constexpr (NP == 3) l[e] = x2;
+    for (int e = 0; e < 8; e += 2) {
+      bf16x2 x0, x1, x2;
+      if constexpr (NP == 2) split2(f32x2{x[e], x[e + 1]}, x0, x1);
+      else split3(f32x2{x[e], x[e + 1]}, x0, x1, x2);
+      h[e] = x0.x; h[e + 1] = x0.y;
+      m[e] = x1.x; m[e + 1] = x1.y;
+      if constexpr (NP == 3) { l[e] = x2.x; l[e + 1] = x2.y; }
     }
   };
   // One operand's items into its LDS planes (row-major [plane][ROWS][ROW]).

@@ -111,12 +111,24 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, const float *__re
                                                     unsigned short *__restrict__ p0,
                                                     unsigned short *__restrict__ p1,
                                                     unsigned short *__restrict__ p2) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    __bf16 h, m, l;
-    split3(x[i], h, m, l);
-    p0[i] = __builtin_bit_cast(unsigned short, h);
-    p1[i] = __builtin_bit_cast(unsigned short, m);
-    if (p2) p2[i] = __builtin_bit_cast(unsigned short, l);
+  // pairs (x[2q], x[2q+1]) through the same pair split the tile body uses
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; 2 * q < n; q += (int64_t)gridDim.x * 256) {
+    const int64_t i = 2 * q;
+    const bool two = i + 1 < n;
+    bf16x2 h, m, l;
+    split3(f32x2{x[i], two ? x[i + 1] : 0.0f}, h, m, l);
+    // bit-cast whole pairs (a bit_cast of a vector element is not
+    // element-indexed in this compiler) and take the halves
+    const unsigned hb = __builtin_bit_cast(unsigned, h), mb = __builtin_bit_cast(unsigned, m),
+                   lb = __builtin_bit_cast(unsigned, l);
+    p0[i] = (unsigned short)(hb & 0xffffu);
+    p1[i] = (unsigned short)(mb & 0xffffu);
+    if (p2) p2[i] = (unsigned short)(lb & 0xffffu);
+    if (two) {
+      p0[i + 1] = (unsigned short)(hb >> 16);
+      p1[i + 1] = (unsigned short)(mb >> 16);
+      if (p2) p2[i + 1] = (unsigned short)(lb >> 16);
+    }
   }
 }
 
@@ -207,7 +219,7 @@ gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
 
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
                       hipStream_t s) {
-  const int64_t want = (n + 255) / 256;
+  const int64_t want = ((n + 1) / 2 + 255) / 256;
   const unsigned grid = (unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192);
   hipLaunchKernelGGL(bx3::split_kernel, dim3(grid), dim3(256), 0, s, n, x, p0, p1, p2);
   return check_launch("split_kernel");
