@@ -536,6 +536,33 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   // ---- peeled epilogue ----------------------------------------------------
   // 32x32 block layout: lane l, element e -> row 8*(e/4) + 4*(l/32) + e%4,
   // column l%32.
+  const int rowsC = Mr < BM ? Mr : BM, colsC = Nr < BN ? Nr : BN;
+  if ((int64_t)BM * ldc * 4 < ((int64_t)1 << 31)) {
+    // Buffer stores with 32-bit offsets: the resource covers the tile's valid
+    // part of C (rows past M fall beyond it and are dropped), columns past N
+    // get an out-of-range lane offset, and the row step of element e is a
+    // wave-uniform scalar offset -- no per-element address arithmetic.
+    const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc(
+        C + (int64_t)m0 * ldc + n0, (short)0, (int)(((int64_t)(rowsC - 1) * ldc + colsC) * 4),
+        kBufferFlags);
+    const int ldc4 = (int)ldc * 4;
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        const int col = wn0 + j * 32 + lrow;
+        const int vbase = col < colsC ? (wm0 + i * 32 + 4 * lgrp) * ldc4 + col * 4 : (int)0x80000000;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int soff = (8 * (e >> 2) + (e & 3)) * ldc4;
+          float v = alpha * acc[i][j][e];
+          if (BETA)
+            v = fmaf(beta, __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rC, vbase, soff, 0)), v);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rC, vbase, soff, 0);
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < G::FM; ++i)
 #pragma unroll
