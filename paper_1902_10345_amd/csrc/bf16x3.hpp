@@ -439,7 +439,7 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   // the LDS stages.
   // The slab grid ends exactly at K (slab s covers [kbase + s*BK, +BK) with
   // kbase = K - KT*BK <= 0), so only slab 0 can be partial; it is loaded with
-  // masking in the prologue.  Loads past the last slab are clamped to it
+  // masking in the prologue when it is.  Loads past the last slab are clamped to it
   // (in-bounds reads whose data is never consumed), so both halves of the loop
   // issue the same instructions on every iteration and each wait covers only
   // the loads it needs.
@@ -450,7 +450,9 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   const int KT = (K + BK - 1) / BK;
   const int kbase = K - KT * BK;
   auto kslab = [&](int sl) { return kbase + (sl < KT ? sl : KT - 1) * BK; };
-  gload(S0{}, Masked{}, kbase);
+  // slab 0 is partial unless K is a multiple of BK (then kbase == 0)
+  if (kbase == 0) gload(S0{}, Fast{}, 0);
+  else gload(S0{}, Masked{}, kbase);
   sstore(S0{}, 0);
   int t = 0;
   if constexpr (G::SETS == 1) {
