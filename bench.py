@@ -268,13 +268,25 @@ def run_profile(torch, mm):
     gws = torch.empty(gws_bytes, dtype=torch.uint8, device="cuda")
     for i in range(5):
         mm.grouped_gemm(arr, len(dev), mm.PATH_3XBF16, None, gws, gws_bytes)
+    del dev, arr, gws
+    Ad, Bd, Cd = (x.double() for x in (A, B, C))
+    for i in range(5):
+        mm.gemm_f64(M, N, K, 1.5, Ad, K, Bd, N, 0.5, Cd, N)
+    del Ad, Bd, Cd
+    ms_, nb_ = 32, 29297
+    sz = ms_ * ms_
+    Ab, Bb, Cb = (torch.rand(nb_ * sz, device="cuda", dtype=torch.float64) for _ in range(3))
+    for i in range(5):
+        mm.gemm_f64_strided_batched(ms_, ms_, ms_, 1.0, Ab, ms_, sz, Bb, ms_, sz, 0.0, Cb, ms_, sz,
+                                    nb_)
+    del Ab, Bb, Cb
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    _log("profile run done: 5 x gemm_bx3, gemm_f32, gemm_fp8 (4096^3), 5 x grouped 512, "
-         "5 x copy of 1 GiB")
+    _log("profile run done: 5 x gemm_bx3, gemm_f32, gemm_fp8, gemm_f64 (4096^3), 5 x grouped 512, "
+         "5 x batched 32^3 x 29297 (binary64), 5 x copy of 1 GiB")
 
 
 def main():
