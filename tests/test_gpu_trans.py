@@ -254,3 +254,36 @@ def test_quick_paths_and_empty_shapes():
         got = d.cpu().numpy()
         assert np.array_equal(si.unstorage(got, o, M, N, ld), (np.float32(0.5) * C0))
         assert np.all(got[si.storage(np.zeros((M, N), np.float32), o, ld, 1.0) == 1.0] == -7.0)
+
+
+@pytest.mark.parametrize("path", ["f32", "3xbf16", "fp8"])
+def test_tensor_helper_takes_transposed_views(path):
+    """ops.gemm passes a column-contiguous view (A.t() of a row-major tensor)
+    as a transposed operand: same bits as the call on materialised copies."""
+    import torch
+    import paper_1902_10345_amd as mm
+    M, N, K = 150, 130, 170
+    At = torch.from_numpy(si.uniform((K, M), 81)).cuda()   # stored K x M
+    Bt = torch.from_numpy(si.uniform((N, K), 82)).cuda()   # stored N x K
+    C0 = torch.from_numpy(si.uniform((M, N), 83)).cuda()
+    got = mm.ops.gemm(At.t(), Bt.t(), C0.clone(), alpha=1.5, beta=0.5, path=path)
+    ref = mm.ops.gemm(At.t().contiguous(), Bt.t().contiguous(), C0.clone(), alpha=1.5, beta=0.5,
+                      path=path)
+    torch.cuda.synchronize()
+    if path == "f32":  # the untransposed call may pick the vector-ALU tile: tolerance
+        d = (got - ref).abs().max().item()
+        assert d <= 1e-4, d
+    else:
+        assert torch.equal(got, ref)
+
+
+def test_tensor_helper_float64():
+    import torch
+    import paper_1902_10345_amd as mm
+    from test_gpu_f64 import _check
+    A, B, C0 = (si.uniform(s, 90 + i).astype(np.float64) for i, s in
+                enumerate(((70, 90), (90, 60), (70, 60))))
+    C = mm.ops.gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                    torch.from_numpy(C0).cuda(), alpha=1.5, beta=0.5)
+    torch.cuda.synchronize()
+    _check(A, B, C0, C.cpu().numpy(), 1.5, 0.5)
