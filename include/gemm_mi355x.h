@@ -189,6 +189,22 @@ gemm_status gemm_f64_strided_batched(int64_t M, int64_t N, int64_t K, double alp
                                      double beta, double *C, int64_t ldc, int64_t stride_c,
                                      int64_t batch, hipStream_t stream);
 
+/* Batched-strided binary32 product (SBSMM, Sec. 6.4, on the binary32 paths):
+ * `batch` independent problems of one shape, problem b reading
+ * A + b*stride_a, B + b*stride_b and updating C + b*stride_c (strides in
+ * elements; zero input strides reuse one matrix).  path: GEMM_PATH_F32
+ * (binary32 products on the FP32 matrix cores) or GEMM_PATH_3XBF16
+ * (n_products 3 or 6, as gemm_f32_3xbf16).  Output matrices must not
+ * overlap: stride_c >= (M-1)*ldc + N when batch > 1.  Layout and quick
+ * returns as gemm_f32; up to 65535 problems per launch.  Arguments: 1 path,
+ * 2 M, 3 N, 4 K, 5 alpha, 6 A, 7 lda, 8 stride_a, 9 B, 10 ldb, 11 stride_b,
+ * 12 beta, 13 C, 14 ldc, 15 stride_c, 16 batch, 17 n_products, 18 stream. */
+gemm_status gemm_strided_batched(int path, int64_t M, int64_t N, int64_t K, float alpha,
+                                 const float *A, int64_t lda, int64_t stride_a, const float *B,
+                                 int64_t ldb, int64_t stride_b, float beta, float *C, int64_t ldc,
+                                 int64_t stride_c, int64_t batch, int n_products,
+                                 hipStream_t stream);
+
 /* gemm_f64 with an explicit tile configuration of GEMM_PATH_F64 (0 <= cfg <
  * gemm_num_configs(GEMM_PATH_F64), or -1 for the default).  Arguments: 1 cfg,
  * then 2..13 as gemm_f64's 1..12. */

@@ -77,6 +77,8 @@ _sig("gemm_f64_run_config", _int, _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, 
      _i64, _vp)
 _sig("gemm_f64_strided_batched", _int, _i64, _i64, _i64, _dbl, _vp, _i64, _i64, _vp, _i64, _i64,
      _dbl, _vp, _i64, _i64, _i64, _vp)
+_sig("gemm_strided_batched", _int, _int, _i64, _i64, _i64, _f32, _vp, _i64, _i64, _vp, _i64, _i64,
+     _f32, _vp, _i64, _i64, _i64, _int, _vp)
 _sig("gemm_ex", _int, _int, _int, _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp,
      _i64, _int, _int, _vp, _sz, _vp)
 
@@ -232,6 +234,13 @@ PATH_F32, PATH_3XBF16, PATH_FP8, PATH_FP8_PREQUANTIZED, PATH_F64 = 0, 1, 2, 3, 4
 def gemm_f64(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     return check(lib.gemm_f64(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C), ldc,
                               stream_handle(stream)))
+
+
+def gemm_strided_batched(path, M, N, K, alpha, A, lda, stride_a, B, ldb, stride_b, beta, C, ldc,
+                         stride_c, batch, n_products=3, stream=None):
+    return check(lib.gemm_strided_batched(path, M, N, K, alpha, ptr(A), lda, stride_a, ptr(B), ldb,
+                                          stride_b, beta, ptr(C), ldc, stride_c, batch, n_products,
+                                          stream_handle(stream)))
 
 
 def gemm_f64_run_config(cfg, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):

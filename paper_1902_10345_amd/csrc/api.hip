@@ -467,6 +467,46 @@ gemm_status gemm_f64_strided_batched(int64_t M, int64_t N, int64_t K, double alp
   return GEMM_STATUS_OK;
 }
 
+gemm_status gemm_strided_batched(int path, int64_t M, int64_t N, int64_t K, float alpha,
+                                 const float *A, int64_t lda, int64_t stride_a, const float *B,
+                                 int64_t ldb, int64_t stride_b, float beta, float *C, int64_t ldc,
+                                 int64_t stride_c, int64_t batch, int n_products,
+                                 hipStream_t stream) {
+  clear_error();
+  const char *fn = "gemm_strided_batched";
+  if (path != GEMM_PATH_F32 && path != GEMM_PATH_3XBF16)
+    return bad_arg(1, fn, "(path) must be GEMM_PATH_F32 or GEMM_PATH_3XBF16");
+  if (M < 0) return bad_arg(2, fn, "(M) must be >= 0");
+  if (N < 0) return bad_arg(3, fn, "(N) must be >= 0");
+  if (K < 0) return bad_arg(4, fn, "(K) must be >= 0");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL || K > 0x7fffffffLL)
+    return bad_arg(M > 0x7fffffffLL ? 2 : N > 0x7fffffffLL ? 3 : 4, fn, "exceeds 2^31-1");
+  if (lda < (K > 1 ? K : 1)) return bad_arg(7, fn, "(lda) must be >= max(1,K)");
+  if (stride_a < 0) return bad_arg(8, fn, "(stride_a) must be >= 0");
+  if (ldb < (N > 1 ? N : 1)) return bad_arg(10, fn, "(ldb) must be >= max(1,N)");
+  if (stride_b < 0) return bad_arg(11, fn, "(stride_b) must be >= 0");
+  if (ldc < (N > 1 ? N : 1)) return bad_arg(14, fn, "(ldc) must be >= max(1,N)");
+  if (batch < 0) return bad_arg(16, fn, "(batch) must be >= 0");
+  if (batch > 1 && M > 0 && N > 0 && stride_c < (M - 1) * ldc + N)
+    return bad_arg(15, fn, "(stride_c) smaller than one output matrix");
+  if (path == GEMM_PATH_3XBF16 && n_products != 3 && n_products != 6)
+    return bad_arg(17, fn, "(n_products) must be 3 or 6");
+  if (M == 0 || N == 0 || batch == 0) return GEMM_STATUS_OK;
+  if (!C) return bad_arg(13, fn, "(C) is NULL");
+  if (alpha == 0.0f || K == 0) return scale_c_batched(M, N, beta, C, ldc, stride_c, batch, stream);
+  if (!A) return bad_arg(6, fn, "(A) is NULL");
+  if (!B) return bad_arg(9, fn, "(B) is NULL");
+  const int cfg = batched_config(path, n_products, M, N, K, batch);
+  for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, batch - b0);
+    GemmArgs g{M, N, K, alpha, beta, A + b0 * stride_a, lda, B + b0 * stride_b, ldb,
+               C + b0 * stride_c, ldc};
+    if (gemm_status st = batched_run(path, cfg, g, stride_a, stride_b, stride_c, nb, stream))
+      return st;
+  }
+  return GEMM_STATUS_OK;
+}
+
 size_t err_norm_workspace_bytes(void) { return errnorm_ws_bytes(); }
 
 gemm_status err_norm_f64(int64_t M, int64_t N, const float *C, int64_t ldc, const double *Cref,

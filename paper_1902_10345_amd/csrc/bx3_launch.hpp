@@ -118,6 +118,53 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   return check_launch("gemm_bx3_kernel");
 }
 
+// A batch of equally shaped problems at fixed element strides: the tiles of
+// one problem in the grid's first dimension (XCD-aware order), the problem in
+// the second.  NP == 1 is the binary32 matrix-core mode.
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA>
+__global__ __launch_bounds__(64 * NW, 1) void gemm_batched_kernel(
+    int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda, int64_t sa,
+    const float *__restrict__ B, int64_t ldb, int64_t sb, float beta, float *__restrict__ C,
+    int64_t ldc, int64_t sc, int tiles_m, int tiles_n) {
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[G::LDS_BYTES / 2];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
+  const int64_t b = blockIdx.y;
+  tile<BM, BN, BK, WM, WN, NP, NW, VEC, BETA>(M, N, K, alpha, A + b * sa, lda, B + b * sb, ldb,
+                                              beta, C + b * sc, ldc, tm * BM, tn * BN, lds);
+}
+
+// Up to 65535 problems per launch (the grid's second dimension).
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
+gemm_status launch_batched(const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc, int batch,
+                           hipStream_t s) {
+  const int tiles_m = (int)((g.M + BM - 1) / BM);
+  const int tiles_n = (int)((g.N + BN - 1) / BN);
+  const int64_t nwg = (int64_t)tiles_m * tiles_n;
+  if (nwg > 0x7fffffff || batch > 65535) {
+    set_error("gemm_strided_batched: too many tiles or problems for one launch");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  if (!offsets_fit<BM, BN, BK, false, false>(g)) {
+    set_error("gemm_strided_batched: lda or ldb too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  // 128-bit A loads need every problem's A 16-byte aligned
+  const bool vec = vector_loads_ok<false, false>(g) && sa % 4 == 0;
+  const bool beta = g.beta != 0.0f;
+  const dim3 grid((unsigned)nwg, (unsigned)batch), block(64 * NW);
+#define MM_LAUNCH(V, BT)                                                                        \
+  hipLaunchKernelGGL((gemm_batched_kernel<BM, BN, BK, WM, WN, NP, NW, V, BT>), grid, block, 0, s, \
+                     (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, sa, g.B, g.ldb, sb,       \
+                     g.beta, g.C, g.ldc, sc, tiles_m, tiles_n)
+  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
+  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
+#undef MM_LAUNCH
+  return check_launch("gemm_batched_kernel");
+}
+
 // The tile configurations that have transposed-operand variants (the ones the
 // library picks by default): 3, 4, 5, 6 and 8 of the split path, both FP32
 // matrix-core tiles.

@@ -217,6 +217,36 @@ gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
   return bx3::launch_f32mfma<128, 128, 16, 64, 64, 4>(g, s);
 }
 
+// Batched-strided products on the matrix-core tiles.  The tile follows the
+// problem's size and the batch's total tile count: 64 x 64 tiles for small
+// problems (128 x 128 for six products and for binary32), otherwise the
+// single-GEMM choice for a problem stacked batch times along M.
+int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, int64_t batch) {
+  if (path == GEMM_PATH_F32) {
+    const int64_t big = ((M + 255) / 256) * ((N + 255) / 256) * batch;
+    return big >= num_cus() ? 0 : 1;  // f32mfma 256 x 256 / 128 x 128
+  }
+  if (M <= 64 && N <= 64) return n_products == 6 ? 5 : 6;
+  return bx3_default_config(M * batch, N, K, n_products);
+}
+
+gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,
+                        int batch, hipStream_t s) {
+  if (path == GEMM_PATH_F32)
+    return cfg == 0 ? bx3::launch_batched<256, 256, 16, 128, 64, 1, 8>(g, sa, sb, sc, batch, s)
+                    : bx3::launch_batched<128, 128, 16, 64, 64, 1, 4>(g, sa, sb, sc, batch, s);
+  switch (cfg) {
+    case 3: return bx3::launch_batched<256, 256, 32, 128, 64, 2, 8>(g, sa, sb, sc, batch, s);
+    case 4: return bx3::launch_batched<256, 256, 16, 128, 64, 3, 8>(g, sa, sb, sc, batch, s);
+    case 5: return bx3::launch_batched<128, 128, 32, 64, 64, 3, 4>(g, sa, sb, sc, batch, s);
+    case 6: return bx3::launch_batched<64, 64, 32, 32, 32, 2, 4>(g, sa, sb, sc, batch, s);
+    case 8: return bx3::launch_batched<128, 128, 16, 64, 64, 2, 4>(g, sa, sb, sc, batch, s);
+    default:
+      set_error("gemm_strided_batched: configuration without a batched variant");
+      return GEMM_STATUS_UNSUPPORTED;
+  }
+}
+
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
                       hipStream_t s) {
   const int64_t want = ((n + 1) / 2 + 255) / 256;

@@ -28,6 +28,38 @@ gemm_status scale_c(int64_t M, int64_t N, float beta, float *C, int64_t ldc, hip
   return check_launch("scale_c_kernel");
 }
 
+// C <- beta*C for a batch of M x N blocks at stride sc (grid.y = problem).
+template <bool BETA>
+__global__ __launch_bounds__(256) void scale_c_batched_kernel(int64_t M, int64_t N, float beta,
+                                                              float *__restrict__ C, int64_t ldc,
+                                                              int64_t sc) {
+  float *Cb = C + (int64_t)blockIdx.y * sc;
+  const int64_t total = M * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / N, j = e - i * N;
+    float *p = Cb + i * ldc + j;
+    *p = BETA ? beta * *p : 0.0f;
+  }
+}
+
+gemm_status scale_c_batched(int64_t M, int64_t N, float beta, float *C, int64_t ldc, int64_t sc,
+                            int64_t batch, hipStream_t s) {
+  const int64_t want = (M * N + 255) / 256;
+  const unsigned gx = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+    const dim3 grid(gx, (unsigned)(batch - b0 < 65535 ? batch - b0 : 65535));
+    if (beta != 0.0f)
+      hipLaunchKernelGGL(scale_c_batched_kernel<true>, grid, dim3(256), 0, s, M, N, beta,
+                         C + b0 * sc, ldc, sc);
+    else
+      hipLaunchKernelGGL(scale_c_batched_kernel<false>, grid, dim3(256), 0, s, M, N, beta,
+                         C + b0 * sc, ldc, sc);
+    if (gemm_status st = check_launch("scale_c_batched_kernel")) return st;
+  }
+  return GEMM_STATUS_OK;
+}
+
 // ------------------------------------------------------- FP64 error norm --
 // Stage 1: kNormBlocks blocks, each walks a fixed grid-stride subset of the
 // MxN elements and reduces (sum d^2, sum ref^2, max ratio) in binary64 with a

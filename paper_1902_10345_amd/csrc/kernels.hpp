@@ -50,6 +50,10 @@ int bx3_splitk_default(int64_t M, int64_t N, int64_t K);
 gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s);
 size_t bx3_splitk_ws_bytes(int64_t M, int64_t N, int splits);
 gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *ws, hipStream_t s);
+// Batched-strided products (binary32 or split precision) on the MFMA tiles.
+int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, int64_t batch);
+gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,
+                        int batch, hipStream_t s);
 gemm_status bx3_split(int64_t n, const float *x, uint16_t *p0, uint16_t *p1, uint16_t *p2,
                       hipStream_t s);
 
@@ -90,6 +94,9 @@ gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t 
 int tuned_config(int path, int n_products, int64_t M, int64_t N, int64_t K);
 double tuned_small_cost();
 
+// C <- beta*C over a batch of MxN blocks at stride sc.
+gemm_status scale_c_batched(int64_t M, int64_t N, float beta, float *C, int64_t ldc, int64_t sc,
+                            int64_t batch, hipStream_t s);
 // C <- beta*C over an MxN block (alpha == 0 or K == 0 quick path).
 gemm_status scale_c(int64_t M, int64_t N, float beta, float *C, int64_t ldc, hipStream_t s);
 

@@ -1,0 +1,106 @@
+"""Batched-strided binary32 products (gemm_strided_batched) on the FP32
+matrix-core path and the split-precision path: every problem of the batch
+against the FP64 oracle, problems placed back to back with gaps (the gaps
+never written), a shared operand (zero stride), bit equality with the
+single-problem entry points, exact integer batches beyond one launch."""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from gpu_util import check_split_result, gamma
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_f32(A, B, C0, C, alpha, beta):
+    ref = oracle.gemm(A, B, alpha=alpha, beta=beta, C0=C0)
+    den = oracle.gemm_abs(A, B, alpha=alpha, beta=beta, C0=C0)
+    cw = oracle.norms(C, ref, den)[3]
+    assert cw <= gamma(A.shape[1]), (cw, gamma(A.shape[1]))
+
+
+def _run(mm, path, n, M, N, K, batch, seed, pad=(0, 0, 0), share_b=False, alpha=1.5, beta=0.5):
+    import torch
+    g = np.random.default_rng(seed)
+    sa, sb, sc = M * K + pad[0], (0 if share_b else K * N + pad[1]), M * N + pad[2]
+    hA = g.uniform(-1, 1, size=batch * sa).astype(np.float32)
+    hB = g.uniform(-1, 1, size=batch * sb if sb else K * N).astype(np.float32)
+    hC = g.uniform(-1, 1, size=batch * sc).astype(np.float32)
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (hA, hB, hC))
+    mm.gemm_strided_batched(path, M, N, K, alpha, dA, K, sa, dB, N, sb, beta, dC, N, sc, batch, n)
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    for b in range(batch):
+        A = hA[b * sa:b * sa + M * K].reshape(M, K)
+        B = hB[b * sb:b * sb + K * N].reshape(K, N)
+        C0 = hC[b * sc:b * sc + M * N].reshape(M, N)
+        C = out[b * sc:b * sc + M * N].reshape(M, N)
+        if path == mm.PATH_3XBF16:
+            check_split_result(oracle, A, B, C0, C, alpha, beta, n)
+        else:
+            _check_f32(A, B, C0, C, alpha, beta)
+        assert np.array_equal(out[b * sc + M * N:(b + 1) * sc], hC[b * sc + M * N:(b + 1) * sc])
+
+
+CASES = [(16, 16, 16, 100), (32, 32, 32, 37), (12, 12, 12, 50), (64, 64, 64, 11),
+         (70, 50, 90, 9), (130, 129, 64, 3), (1, 1, 5, 7), (33, 17, 40, 13)]
+
+
+@pytest.mark.parametrize("M,N,K,batch", CASES)
+@pytest.mark.parametrize("n", [3, 6])
+def test_split_path_parity(M, N, K, batch, n):
+    import paper_1902_10345_amd as mm
+    _run(mm, mm.PATH_3XBF16, n, M, N, K, batch, M + 7 * N + K + batch)
+    _run(mm, mm.PATH_3XBF16, n, M, N, K, batch, M + N + K + batch + 1, pad=(3, 5, 7))
+
+
+@pytest.mark.parametrize("M,N,K,batch", CASES)
+def test_f32_path_parity(M, N, K, batch):
+    import paper_1902_10345_amd as mm
+    _run(mm, mm.PATH_F32, 3, M, N, K, batch, 3 * M + N + K + batch, pad=(1, 2, 3))
+
+
+def test_shared_b_and_one_problem_equals_the_single_gemm():
+    import torch
+    import paper_1902_10345_amd as mm
+    _run(mm, mm.PATH_3XBF16, 3, 40, 24, 33, 20, 5, share_b=True)
+    M, N, K = 130, 140, 150
+    A, B, C0 = si.uniform((M, K), 51), si.uniform((K, N), 52), si.uniform((M, N), 53)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for n in (3, 6):
+        d1, d2 = torch.from_numpy(C0.copy()).cuda(), torch.from_numpy(C0.copy()).cuda()
+        mm.gemm_f32_3xbf16(M, N, K, 1.5, dA, K, dB, N, 0.5, d1, N, n)
+        mm.gemm_strided_batched(mm.PATH_3XBF16, M, N, K, 1.5, dA, K, 0, dB, N, 0, 0.5, d2, N, 0, 1, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(d1.cpu().numpy(), d2.cpu().numpy()), n
+
+
+@pytest.mark.parametrize("path", ["f32", "3xbf16"])
+def test_more_problems_than_one_launch_exact(path):
+    import torch
+    import paper_1902_10345_amd as mm
+    code = mm.PATH_F32 if path == "f32" else mm.PATH_3XBF16
+    M = N = K = 2
+    batch = 65540
+    g = np.random.default_rng(61)
+    hA = g.integers(-9, 10, size=(batch, M, K)).astype(np.float32)
+    hB = g.integers(-9, 10, size=(batch, K, N)).astype(np.float32)
+    hC = g.integers(-9, 10, size=(batch, M, N)).astype(np.float32)
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (hA, hB, hC))
+    mm.gemm_strided_batched(code, M, N, K, 2.0, dA, K, M * K, dB, N, K * N, -1.0, dC, N, M * N, batch, 3)
+    torch.cuda.synchronize()
+    want = 2.0 * np.matmul(hA.astype(np.float64), hB.astype(np.float64)) - hC
+    assert np.array_equal(dC.cpu().numpy().astype(np.float64), want)
+
+
+def test_quick_path_scales_every_problem():
+    import torch
+    import paper_1902_10345_amd as mm
+    M, N, batch = 5, 6, 70000
+    hC = si.uniform((batch, M * N), 71).reshape(-1)
+    d = torch.from_numpy(hC.copy()).cuda()
+    mm.gemm_strided_batched(mm.PATH_3XBF16, M, N, 0, 1.0, None, 1, 0, None, N, 0, 0.5, d, N, M * N,
+                            batch, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy(), np.float32(0.5) * hC)

@@ -283,3 +283,25 @@ def test_f64_argument_codes_and_configs():
     assert sb(*args(A=None)) == -5 and sb(*args(B=None)) == -8
     assert sb(*args(batch=0, A=None, B=None, C=None)) == 0
     assert sb(*args(sc=0, batch=1, A=None)) == -5   # one problem: any output stride
+
+
+def test_strided_batched_argument_codes():
+    import paper_1902_10345_amd as mm
+    sb = mm.lib.gemm_strided_batched
+    base = dict(path=mm.PATH_3XBF16, M=4, N=4, K=4, alpha=1.0, A=F, lda=4, sa=16, B=F, ldb=4,
+                sb=16, beta=0.0, C=F, ldc=4, sc=16, batch=3, n=3)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return sb(a["path"], a["M"], a["N"], a["K"], a["alpha"], a["A"], a["lda"], a["sa"], a["B"],
+                  a["ldb"], a["sb"], a["beta"], a["C"], a["ldc"], a["sc"], a["batch"], a["n"], None)
+
+    assert call(path=mm.PATH_FP8) == -1 and call(path=mm.PATH_F64) == -1
+    assert call(M=-1) == -2 and call(N=-1) == -3 and call(K=-1) == -4
+    assert call(lda=3) == -7 and call(sa=-1) == -8
+    assert call(ldb=3) == -10 and call(sb=-1) == -11
+    assert call(ldc=3) == -14 and call(sc=15) == -15 and call(batch=-1) == -16
+    assert call(n=5) == -17
+    assert call(path=mm.PATH_F32, n=5, C=None) == -13   # n_products ignored on the FP32 path
+    assert call(A=None) == -6 and call(B=None) == -9
+    assert call(batch=0, A=None, B=None, C=None) == 0
