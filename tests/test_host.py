@@ -305,3 +305,23 @@ def test_strided_batched_argument_codes():
     assert call(path=mm.PATH_F32, n=5, C=None) == -13   # n_products ignored on the FP32 path
     assert call(A=None) == -6 and call(B=None) == -9
     assert call(batch=0, A=None, B=None, C=None) == 0
+
+
+def test_strides_beyond_32_bit_tile_offsets_are_refused_before_launch():
+    """Leading dimensions whose tile panels exceed 2^31 bytes cannot be
+    addressed with the kernels' 32-bit buffer offsets: the launchers refuse
+    them (GEMM_STATUS_UNSUPPORTED) before anything is enqueued -- these calls
+    never touch the (dummy) pointers."""
+    import paper_1902_10345_amd as mm
+    lib = mm.lib
+    big = 1 << 24   # 64-row tiles: 64 x 2^24 floats x 4 B = 2^32 bytes
+    assert lib.gemm_f32_3xbf16(300, 300, 300, 1.0, F, big, F, 300, 0.0, F, 300, 3, None) == \
+        mm.STATUS_UNSUPPORTED
+    assert "32-bit" in mm.gemm_last_error()
+    assert lib.gemm_f32_3xbf16(300, 300, 300, 1.0, F, 300, F, big * 8, 0.0, F, 300, 3, None) == \
+        mm.STATUS_UNSUPPORTED
+    assert lib.gemm_f64(300, 300, 300, 1.0, F, big, F, 300, 0.0, F, 300, None) == mm.STATUS_UNSUPPORTED
+    assert lib.gemm_ex(mm.ROW_MAJOR, mm.TRANS, mm.NO_TRANS, 300, 300, 300, 1.0, F, big * 8, F, 300,
+                       0.0, F, 300, mm.PATH_3XBF16, 3, None, 0, None) == mm.STATUS_UNSUPPORTED
+    assert lib.gemm_strided_batched(mm.PATH_3XBF16, 300, 300, 300, 1.0, F, big, 0, F, 300, 0, 0.0,
+                                    F, 300, 90000, 2, 3, None) == mm.STATUS_UNSUPPORTED
