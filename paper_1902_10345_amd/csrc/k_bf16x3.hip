@@ -223,11 +223,14 @@ gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
 // single-GEMM choice for a problem stacked batch times along M.
 int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, int64_t batch) {
   if (path == GEMM_PATH_F32) {
-    const int64_t big = ((M + 255) / 256) * ((N + 255) / 256) * batch;
-    return big >= num_cus() ? 0 : 1;  // f32mfma 256 x 256 / 128 x 128
+    const int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
+    if (tiles <= 0) return 1;
+    return batch >= (num_cus() + tiles - 1) / tiles ? 0 : 1;  // f32mfma 256 x 256 / 128 x 128
   }
   if (M <= 64 && N <= 64) return n_products == 6 ? 5 : 6;
-  return bx3_default_config(M * batch, N, K, n_products);
+  // M stacked batch times (saturated: only the tile count's size matters)
+  const int64_t stacked = M <= 0 ? 0 : batch > ((int64_t)1 << 40) / M ? ((int64_t)1 << 40) : M * batch;
+  return bx3_default_config(stacked, N, K, n_products);
 }
 
 gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,

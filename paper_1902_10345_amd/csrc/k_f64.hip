@@ -454,7 +454,13 @@ const TileConfig &f64_config(int i) { return kF64Configs[i].t; }
 int f64_default_config(int64_t M, int64_t N, int64_t K, int64_t batch) {
   (void)K;
   const int64_t cus = num_cus();
-  auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch; };
+  // tile count of the whole batch, saturated (only its size relative to the
+  // compute units matters)
+  auto tiles = [&](int bm, int bn) {
+    const int64_t t = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+    if (t <= 0 || batch <= 0) return (int64_t)0;
+    return batch > ((int64_t)1 << 40) / t ? ((int64_t)1 << 40) : t * batch;
+  };
   // batches of small problems: one wave per problem
   if (batch > 1 && M <= 64 && N <= 64) return M <= 16 && N <= 16 ? 3 : (M <= 32 && N <= 32 ? 4 : 5);
   // 64 x 64 tiles for problems that would fill little of a 128 x 128 tile,

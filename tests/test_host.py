@@ -325,3 +325,11 @@ def test_strides_beyond_32_bit_tile_offsets_are_refused_before_launch():
                        0.0, F, 300, mm.PATH_3XBF16, 3, None, 0, None) == mm.STATUS_UNSUPPORTED
     assert lib.gemm_strided_batched(mm.PATH_3XBF16, 300, 300, 300, 1.0, F, big, 0, F, 300, 0, 0.0,
                                     F, 300, 90000, 2, 3, None) == mm.STATUS_UNSUPPORTED
+
+
+def test_default_config_of_empty_shapes():
+    import paper_1902_10345_amd as mm
+    for path in (mm.PATH_F32, mm.PATH_3XBF16, mm.PATH_FP8, mm.PATH_F64):
+        for shape in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (0, 0, 0)]:
+            c = mm.gemm_default_config(path, *shape)
+            assert 0 <= c < mm.gemm_num_configs(path), (path, shape, c)
