@@ -163,7 +163,9 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   const int64_t cus = num_cus();
   const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
   if (n_products == 6) return big >= cus ? 4 : 5;
-  if (big >= cus) return 3;  // 256 x 256 x 32: 1-2 % ahead of the 16-deep slabs, every run
+  // 256 x 256 x 16 (two register sets): 1.5-2.4 % ahead of the 32-deep slabs
+  // at 4096^3, 8192 x 2048 x 4096 and 8192^2 x 4096 (same box, alternating)
+  if (big >= cus) return 0;
   // measured: once 256 x 256 tiles leave CUs idle, 128 x 128 x 16 tiles win
   // while they still fill every CU, below that 64 x 64 tiles
   const int64_t small = ((M + 127) / 128) * ((N + 127) / 128);
@@ -239,6 +241,7 @@ gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_
     return cfg == 0 ? bx3::launch_batched<256, 256, 16, 128, 64, 1, 8>(g, sa, sb, sc, batch, s)
                     : bx3::launch_batched<128, 128, 16, 64, 64, 1, 4>(g, sa, sb, sc, batch, s);
   switch (cfg) {
+    case 0: return bx3::launch_batched<256, 256, 16, 128, 64, 2, 8>(g, sa, sb, sc, batch, s);
     case 3: return bx3::launch_batched<256, 256, 32, 128, 64, 2, 8>(g, sa, sb, sc, batch, s);
     case 4: return bx3::launch_batched<256, 256, 16, 128, 64, 3, 8>(g, sa, sb, sc, batch, s);
     case 5: return bx3::launch_batched<128, 128, 32, 64, 64, 3, 4>(g, sa, sb, sc, batch, s);
