@@ -166,12 +166,13 @@ gemm_status launch_batched(const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc
 }
 
 // The tile configurations that have transposed-operand variants (the ones the
-// library picks by default): 0, 3, 4, 5, 6 and 8 of the split path, both FP32
-// matrix-core tiles.
+// library picks by default): 0, 2, 3, 4, 5, 6 and 8 of the split path, both
+// FP32 matrix-core tiles.
 template <bool TA, bool TB>
 gemm_status bx3_run_trans(const GemmArgs &g, int cfg, hipStream_t s) {
   switch (cfg) {
     case 0: return launch<256, 256, 16, 128, 64, 2, 8, TA, TB>(g, s);
+    case 2: return launch<256, 128, 32, 64, 64, 2, 8, TA, TB>(g, s);
     case 3: return launch<256, 256, 32, 128, 64, 2, 8, TA, TB>(g, s);
     case 4: return launch<256, 256, 16, 128, 64, 3, 8, TA, TB>(g, s);
     case 5: return launch<128, 128, 32, 64, 64, 3, 4, TA, TB>(g, s);

@@ -159,17 +159,23 @@ const TileConfig &bx3_config(int i) { return kBx3Configs[i].t; }
 int bx3_config_products(int i) { return kBx3Configs[i].np == 2 ? 3 : 6; }
 
 int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
-  (void)K;
   const int64_t cus = num_cus();
-  const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
+  auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
+  const int64_t big = tiles(256, 256);
   if (n_products == 6) return big >= cus ? 4 : 5;
-  // 256 x 256 x 16 (two register sets): 1.5-2.4 % ahead of the 32-deep slabs
-  // at 4096^3, 8192 x 2048 x 4096 and 8192^2 x 4096 (same box, alternating)
+  // 256 x 256 x 16: 1.5-2.4 % ahead of the 32-deep slabs at 4096^3,
+  // 8192 x 2048 x 4096 and 8192^2 x 4096 (same box, alternating)
   if (big >= cus) return 0;
-  // measured: once 256 x 256 tiles leave CUs idle, 128 x 128 x 16 tiles win
-  // while they still fill every CU, below that 64 x 64 tiles
-  const int64_t small = ((M + 127) / 128) * ((N + 127) / 128);
-  if (small >= cus) return 8;
+  // Below that, measured on one box (all configurations, alternating): the
+  // 8-wave 256 x 128 tiles win by 9-11 % when they come to about one wave of
+  // the machine (4096 x 2048^2, 2560^3, 2048 x 4096^2); 128 x 128 x 16 tiles
+  // while there are at least two per CU, or one per CU with a deep
+  // reduction (2048^2 x 4096); 64 x 64 tiles otherwise (2048^3, 2048^2 x 1024,
+  // and everything smaller).
+  const int64_t mid = tiles(256, 128);
+  if (mid * 4 >= cus * 3 && mid <= cus) return 2;
+  const int64_t small = tiles(128, 128);
+  if (small >= 2 * cus || (small >= cus && K >= 4096)) return 8;
   return 6;
 }
 
@@ -242,6 +248,7 @@ gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_
                     : bx3::launch_batched<128, 128, 16, 64, 64, 1, 4>(g, sa, sb, sc, batch, s);
   switch (cfg) {
     case 0: return bx3::launch_batched<256, 256, 16, 128, 64, 2, 8>(g, sa, sb, sc, batch, s);
+    case 2: return bx3::launch_batched<256, 128, 32, 64, 64, 2, 8>(g, sa, sb, sc, batch, s);
     case 3: return bx3::launch_batched<256, 256, 32, 128, 64, 2, 8>(g, sa, sb, sc, batch, s);
     case 4: return bx3::launch_batched<256, 256, 16, 128, 64, 3, 8>(g, sa, sb, sc, batch, s);
     case 5: return bx3::launch_batched<128, 128, 32, 64, 64, 3, 4>(g, sa, sb, sc, batch, s);

@@ -37,8 +37,8 @@ const TileConfig &bx3_config(int i);
 int bx3_config_products(int i);
 int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products);
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s);
-// Transposed-operand variants (B^T, A^T, both), for configurations 0, 3, 4,
-// 5, 6 and 8; bx3_run and f32mfma_run dispatch to them from g.ta / g.tb.
+// Transposed-operand variants (B^T, A^T, both), for configurations 0, 2, 3,
+// 4, 5, 6 and 8; bx3_run and f32mfma_run dispatch to them from g.ta / g.tb.
 gemm_status bx3_run_nt(const GemmArgs &g, int cfg, hipStream_t s);
 gemm_status bx3_run_tn(const GemmArgs &g, int cfg, hipStream_t s);
 gemm_status bx3_run_tt(const GemmArgs &g, int cfg, hipStream_t s);

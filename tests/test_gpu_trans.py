@@ -201,9 +201,11 @@ def test_fp8_column_major_against_dequantised_oracle(ta, tb, outliers):
     assert cw <= fp8_bound(K), (cw, fp8_bound(K))
 
 
-# Shapes on which the library picks the machine-filling tiles: 128 x 128 x 16
-# (three products) and the 256 x 256 tiles (three and six products, FP32).
-@pytest.mark.parametrize("M,N,K", [(2085, 1998, 515), (4101, 4093, 300)])
+# Shapes on which the library picks the larger tiles: 256 x 128 x 32 and
+# 128 x 128 x 16 (three products), the 256 x 256 tiles (three and six
+# products, FP32), and the 64 x 64 tile next to them.
+@pytest.mark.parametrize("M,N,K", [(2085, 1998, 515), (4101, 4093, 300), (2560, 2560, 300),
+                                   (3000, 3000, 300)])
 @pytest.mark.parametrize("o", ORDERS)
 @pytest.mark.parametrize("ta,tb", FLAGS[1:])
 def test_large_tiles_sampled_rows(M, N, K, o, ta, tb):
