@@ -167,15 +167,16 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   // 8192 x 2048 x 4096 and 8192^2 x 4096 (same box, alternating)
   if (big >= cus) return 0;
   // Below that, measured on one box (all configurations, alternating): the
-  // 8-wave 256 x 128 tiles win by 9-11 % when they come to about one wave of
-  // the machine (4096 x 2048^2, 2560^3, 2048 x 4096^2); 128 x 128 x 16 tiles
-  // while there are at least two per CU, or one per CU with a deep
-  // reduction (2048^2 x 4096); 64 x 64 tiles otherwise (2048^3, 2048^2 x 1024,
-  // and everything smaller).
+  // 8-wave 256 x 128 tiles win by 7-11 % when they come to about one wave of
+  // the machine (4096 x 2048^2, 2560^3, 2048 x 4096^2; with and without
+  // beta); 128 x 128 x 16 tiles while they fill every CU (at one tile per CU
+  // they win by 6 % with beta == 0, the paper's C = A*B at 2048^3, and lose
+  // by 4 % with beta != 0); 64 x 64 tiles below that.
+  (void)K;
   const int64_t mid = tiles(256, 128);
   if (mid * 4 >= cus * 3 && mid <= cus) return 2;
   const int64_t small = tiles(128, 128);
-  if (small >= 2 * cus || (small >= cus && K >= 4096)) return 8;
+  if (small >= cus) return 8;
   return 6;
 }
 
