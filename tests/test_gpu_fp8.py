@@ -60,7 +60,9 @@ def _quantize(mm, A, B, lda=None):
 
 
 @pytest.mark.parametrize("M,N,K,outliers", [(96, 80, 200, "none"), (257, 130, 1000, "A"),
-                                            (64, 300, 129, "B"), (1, 1, 1, "none")])
+                                            (64, 300, 129, "B"), (1, 1, 1, "none"),
+                                            (70, 50, 450, "A"), (33, 40, 1500, "B"),
+                                            (6, 9, 4097, "none")])
 def test_quantiser_is_bitwise_the_oracle(M, N, K, outliers):
     import paper_1902_10345_amd as mm
     A, B, _ = si.fp8_workload(M, N, K, seed=M + N + K, outliers=outliers)
