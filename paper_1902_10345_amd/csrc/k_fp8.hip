@@ -84,16 +84,40 @@ __device__ __forceinline__ float quot(float v, float s, float r) {
   return __builtin_copysignf(__builtin_fmaf(rem, r, q0), v);
 }
 
-// Codes of 4 consecutive elements k .. k+3 of a row (zero past K), packed.
-template <bool FAST, typename I>
-__device__ __forceinline__ uint32_t encode4(const float (&v)[4], I k, I K, float s, float r) {
-  uint32_t word = 0;
+// Codes of 4 values, packed little-endian (element 0 in the low byte).  The
+// callers load values past the end of a row as +0, whose code is 0.
+//  MODE 2: hardware conversion.  v_cvt_pk_fp8_f32 rounds to nearest even onto
+//          E4M3; after clamping to [-448, 448] it gives the codes of
+//          e4m3_encode for every non-NaN input (compared over all 2^32
+//          binary32 inputs on gfx950), so this mode is used only for values
+//          that hold no NaN, with a quotient from quot<true>.
+//  MODE 1: quot<true> and e4m3_encode (NaN present).
+//  MODE 0: the division and e4m3_encode (scale outside [2^-60, 2^60]).
+template <int MODE>
+using Mode = std::integral_constant<int, MODE>;
+
+template <int MODE>
+__device__ __forceinline__ uint32_t codes4(const float (&v)[4], float s, float r) {
+  if constexpr (MODE == 2) {
+    float c[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const uint32_t in = 0u - (uint32_t)(k + e < K);  // mask: code or zero, no branch
-    word |= (e4m3_encode(quot<FAST>(v[e], s, r)) & in) << (8 * e);
+    for (int e = 0; e < 4; ++e) c[e] = __builtin_amdgcn_fmed3f(quot<true>(v[e], s, r), -448.0f, 448.0f);
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], lo, true);
+  } else {
+    uint32_t word = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) word |= e4m3_encode(quot<MODE == 1>(v[e], s, r)) << (8 * e);
+    return word;
   }
-  return word;
+}
+
+// Runs emit(Mode<m>{}) with the mode that the scale and the lane's NaN flag allow.
+template <typename F>
+__device__ __forceinline__ void with_mode(float s, bool has_nan, F &&emit) {
+  if (!quot_ok(s)) emit(Mode<0>{});
+  else if (has_nan) emit(Mode<1>{});
+  else emit(Mode<2>{});
 }
 
 __device__ __forceinline__ float warp_max(float v) {
@@ -121,8 +145,9 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(int M, int K, int64_t K
   if (threadIdx.x == 0) sa[i] = s;
   const float r = 1.0f / s;
   uint8_t *q = qa + (int64_t)i * Kp;
-  auto emit = [&](auto fast) {
-    constexpr bool F = decltype(fast)::value;
+  // Rows this long are re-read here; the NaN-safe mode 1 serves every value.
+  auto emit = [&](auto mode) {
+    constexpr int MD = decltype(mode)::value;
     for (int64_t k0 = (int64_t)threadIdx.x * 16; k0 < Kp; k0 += 256 * 16) {
       uint32_t w[4];
 #pragma unroll
@@ -131,13 +156,12 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(int M, int K, int64_t K
         float v[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] = k + e < K ? row[k + e] : 0.0f;
-        w[g] = encode4<F>(v, k, (int64_t)K, s, r);
+        w[g] = codes4<MD>(v, s, r);
       }
       *reinterpret_cast<uint4 *>(q + k0) = make_uint4(w[0], w[1], w[2], w[3]);
     }
   };
-  if (quot_ok(s)) emit(std::true_type{});
-  else emit(std::false_type{});
+  with_mode(s, true, emit);
 }
 
 // Single-pass variant for rows of at most 256*4*CH elements: the row stays
@@ -154,6 +178,7 @@ __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int M, int K, int64
   const float *row = A + (int64_t)i * lda;
   float v[CH][4];
   float m = 0.0f;
+  bool nan = false;
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int k = 4 * (int)threadIdx.x + 1024 * j;
@@ -165,7 +190,10 @@ __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int M, int K, int64
       for (int e = 0; e < 4; ++e) v[j][e] = k + e < K ? row[k + e] : 0.0f;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) m = fmaxf(m, fabsf(v[j][e]));
+    for (int e = 0; e < 4; ++e) {
+      m = fmaxf(m, fabsf(v[j][e]));
+      nan |= v[j][e] != v[j][e];
+    }
   }
   m = warp_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -175,16 +203,14 @@ __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int M, int K, int64
   if (threadIdx.x == 0) sa[i] = s;
   const float r = 1.0f / s;
   uint8_t *q = qa + (int64_t)i * Kp;
-  auto emit = [&](auto fast) {
-    constexpr bool F = decltype(fast)::value;
+  auto emit = [&](auto mode) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const int k = 4 * (int)threadIdx.x + 1024 * j;
-      if (k < Kp) *reinterpret_cast<uint32_t *>(q + k) = encode4<F>(v[j], k, K, s, r);
+      if (k < Kp) *reinterpret_cast<uint32_t *>(q + k) = codes4<decltype(mode)::value>(v[j], s, r);
     }
   };
-  if (quot_ok(s)) emit(std::true_type{});
-  else emit(std::false_type{});
+  with_mode(s, nan, emit);
 }
 
 // One wave per row (four rows per workgroup) for rows of at most 256 * CH
@@ -203,6 +229,7 @@ __global__ __launch_bounds__(256) void quant_rows_wave_kernel(int M, int K, int6
   const float *row = A + (int64_t)i * lda;
   float v[CH][4];
   float m = 0.0f;
+  bool nan = false;
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int k = 4 * lane + 256 * j;
@@ -214,23 +241,24 @@ __global__ __launch_bounds__(256) void quant_rows_wave_kernel(int M, int K, int6
       for (int e = 0; e < 4; ++e) v[j][e] = k + e < K ? row[k + e] : 0.0f;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) m = fmaxf(m, fabsf(v[j][e]));
+    for (int e = 0; e < 4; ++e) {
+      m = fmaxf(m, fabsf(v[j][e]));
+      nan |= v[j][e] != v[j][e];
+    }
   }
   m = warp_max(m);
   const float s = (m == 0.0f) ? 1.0f : m / 448.0f;
   if (lane == 0) sa[i] = s;
   const float r = 1.0f / s;
   uint8_t *q = qa + (int64_t)i * Kp;
-  auto emit = [&](auto fast) {
-    constexpr bool F = decltype(fast)::value;
+  auto emit = [&](auto mode) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const int k = 4 * lane + 256 * j;
-      if (k < Kp) *reinterpret_cast<uint32_t *>(q + k) = encode4<F>(v[j], k, K, s, r);
+      if (k < Kp) *reinterpret_cast<uint32_t *>(q + k) = codes4<decltype(mode)::value>(v[j], s, r);
     }
   };
-  if (quot_ok(s)) emit(std::true_type{});
-  else emit(std::false_type{});
+  with_mode(s, nan, emit);
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
@@ -294,18 +322,25 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t
     if (blockIdx.x == 0 && ty == 0) sb[j] = s;
   }
   const float rs = 1.0f / s;
-  auto emit = [&](auto fast) {
-    constexpr bool F = decltype(fast)::value;
-#pragma unroll 4
-    for (int r = ty; r < 64; r += 4) {
-      const int k = kb + r;
-      const bool in = k < K && j < N;
-      const float x = in ? B[(int64_t)k * ldb + j] : 0.0f;
-      tileT[tx][r] = (uint8_t)(e4m3_encode(quot<F>(x, s, rs)) & (0u - (uint32_t)in));
+  // Lane (tx, ty) holds rows ty + 4i (i < 16) of its column.
+  float x[16];
+  bool nan = false;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int k = kb + ty + 4 * i;
+    x[i] = (k < K && j < N) ? B[(int64_t)k * ldb + j] : 0.0f;
+    nan |= x[i] != x[i];
+  }
+  auto emit = [&](auto mode) {
+#pragma unroll
+    for (int i = 0; i < 16; i += 4) {
+      const float g[4] = {x[i], x[i + 1], x[i + 2], x[i + 3]};
+      const uint32_t w = codes4<decltype(mode)::value>(g, s, rs);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tileT[tx][ty + 4 * (i + e)] = (uint8_t)(w >> (8 * e));
     }
   };
-  if (quot_ok(s)) emit(std::true_type{});  // per column: lanes may differ
-  else emit(std::false_type{});
+  with_mode(s, nan, emit);  // per column: lanes may take different modes
   __syncthreads();
   // 64 rows (n) x 64 bytes (k): each lane stores 16 bytes.
   const int row = threadIdx.x >> 2, seg = (threadIdx.x & 3) * 16;

@@ -76,6 +76,39 @@ def test_quantiser_is_bitwise_the_oracle(M, N, K, outliers):
     assert not qa[:, K:].any() and not qbT[:, K:].any()
 
 
+@pytest.mark.parametrize("M,N,K", [(40, 36, 200), (40, 36, 1000), (12, 20, 9000)])
+def test_quantiser_special_values_are_bitwise_the_oracle(M, N, K):
+    """Rows and columns with NaN, infinities, signed zeros and scales of
+    2^-70 and 2^70 (outside the range where the quotient is formed from the
+    reciprocal) next to ordinary ones: every code and scale as the oracle's.
+    K = 200, 1000 and 9000 reach the three row-quantiser shapes."""
+    import paper_1902_10345_amd as mm
+    g = np.random.default_rng(K + 1)
+    A = g.standard_normal((M, K)).astype(np.float32)
+    B = g.standard_normal((K, N)).astype(np.float32)
+    A[1] *= np.float32(2.0 ** -70)
+    A[2] *= np.float32(2.0 ** 70)
+    A[3, 5] = np.nan
+    A[4, 7] = np.inf
+    A[5, ::3] = -0.0
+    A[6] = 0.0
+    A[6, 0] = -0.0
+    A[7] *= np.float32(2.0 ** -58)
+    A[8, -1] = -np.nan
+    B[:, 1] *= np.float32(2.0 ** -70)
+    B[:, 2] *= np.float32(2.0 ** 70)
+    B[9, 3] = np.nan
+    B[4, 4] = -np.inf
+    B[::2, 5] = -0.0
+    B[:, 6] *= np.float32(2.0 ** 58)
+    _, _, qa, qbT, sa, sb, Kp = _quantize(mm, A, B)
+    rsa, rsb = oracle.fp8_scales_rows(A), oracle.fp8_scales_cols(B)
+    assert np.array_equal(sa, rsa) and np.array_equal(sb, rsb)
+    assert np.array_equal(qa[:, :K], oracle.fp8_quantize_rows(A, rsa))
+    assert np.array_equal(qbT[:, :K].T, oracle.fp8_quantize_cols(B, rsb))
+    assert not qa[:, K:].any() and not qbT[:, K:].any()
+
+
 # The matrix core's internal summation of one 64-deep FP8 block is not
 # specified to IEEE sequential-rounding accuracy; componentwise errors of up to
 # 2.4 gamma_K against the dequantised oracle were measured, so the pin allows 8.
