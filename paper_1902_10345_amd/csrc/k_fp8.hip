@@ -311,7 +311,9 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t
                                                            const uint32_t *__restrict__ amax_bits,
                                                            uint8_t *__restrict__ qbT,
                                                            float *__restrict__ sb) {
-  __shared__ uint8_t tileT[64][64 + 16];
+  // Rows of 68 bytes (17 words): the 64 lanes of a wave store to 64 different
+  // banks when each writes one word of its own row.
+  __shared__ __attribute__((aligned(16))) uint8_t tileT[64][64 + 4];
   const int kb = blockIdx.x * 64, nb = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int j = nb + tx;
@@ -322,12 +324,13 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t
     if (blockIdx.x == 0 && ty == 0) sb[j] = s;
   }
   const float rs = 1.0f / s;
-  // Lane (tx, ty) holds rows ty + 4i (i < 16) of its column.
+  // Lane (tx, ty) holds rows 16 ty + i (i < 16) of its column; for each i the
+  // wave reads 64 consecutive floats of one row.
   float x[16];
   bool nan = false;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int k = kb + ty + 4 * i;
+    const int k = kb + 16 * ty + i;
     x[i] = (k < K && j < N) ? B[(int64_t)k * ldb + j] : 0.0f;
     nan |= x[i] != x[i];
   }
@@ -335,9 +338,7 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t
 #pragma unroll
     for (int i = 0; i < 16; i += 4) {
       const float g[4] = {x[i], x[i + 1], x[i + 2], x[i + 3]};
-      const uint32_t w = codes4<decltype(mode)::value>(g, s, rs);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) tileT[tx][ty + 4 * (i + e)] = (uint8_t)(w >> (8 * e));
+      *reinterpret_cast<uint32_t *>(&tileT[tx][16 * ty + i]) = codes4<decltype(mode)::value>(g, s, rs);
     }
   };
   with_mode(s, nan, emit);  // per column: lanes may take different modes
