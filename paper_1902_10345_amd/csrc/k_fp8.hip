@@ -120,6 +120,15 @@ __device__ __forceinline__ void with_mode(float s, bool has_nan, F &&emit) {
   else emit(Mode<2>{});
 }
 
+// The row quantisers also clear nzero words (the column-amax words that a
+// later column quantisation on the same stream accumulates into), one per
+// thread of the grid, so that it needs no clearing launch of its own.  The
+// host passes nzero = 0 when the grid has fewer threads than words.
+__device__ __forceinline__ void clear_words(uint32_t *__restrict__ p, int64_t n) {
+  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < n) p[z] = 0u;
+}
+
 __device__ __forceinline__ float warp_max(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -131,7 +140,9 @@ __device__ __forceinline__ float warp_max(float v) {
 __global__ __launch_bounds__(256) void quant_rows_kernel(int M, int K, int64_t Kp,
                                                          const float *__restrict__ A, int64_t lda,
                                                          uint8_t *__restrict__ qa,
-                                                         float *__restrict__ sa) {
+                                                         float *__restrict__ sa,
+                                                         uint32_t *__restrict__ zero, int64_t nzero) {
+  clear_words(zero, nzero);
   __shared__ float red[4];
   const int i = blockIdx.x;
   const float *row = A + (int64_t)i * lda;
@@ -172,7 +183,10 @@ template <int CH, bool VEC>
 __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int M, int K, int64_t Kp,
                                                              const float *__restrict__ A,
                                                              int64_t lda, uint8_t *__restrict__ qa,
-                                                             float *__restrict__ sa) {
+                                                             float *__restrict__ sa,
+                                                             uint32_t *__restrict__ zero,
+                                                             int64_t nzero) {
+  clear_words(zero, nzero);
   __shared__ float red[4];
   const int i = blockIdx.x;
   const float *row = A + (int64_t)i * lda;
@@ -222,7 +236,10 @@ template <int CH, bool VEC>
 __global__ __launch_bounds__(256) void quant_rows_wave_kernel(int M, int K, int64_t Kp,
                                                               const float *__restrict__ A,
                                                               int64_t lda, uint8_t *__restrict__ qa,
-                                                              float *__restrict__ sa) {
+                                                              float *__restrict__ sa,
+                                                              uint32_t *__restrict__ zero,
+                                                              int64_t nzero) {
+  clear_words(zero, nzero);
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (i >= M) return;
@@ -680,25 +697,32 @@ size_t fp8_ws_bytes(int64_t M, int64_t N, int64_t K) { return fp8::layout(M, N, 
 int64_t fp8_kp(int64_t K) { return fp8::layout(0, 0, K).Kp; }
 
 // Row quantisation: R rows of K binary32 values (row stride ld) -> per-row
-// scales and codes in rows of Kp bytes (k contiguous).
+// scales and codes in rows of Kp bytes (k contiguous).  zero: nzero words that
+// the launch also clears when its grid has a thread for each (for a later
+// quant_cols on the same stream); *cleared tells whether it did.
 static gemm_status quant_rows(int64_t R, int64_t K, int64_t Kp, const float *P, int64_t ld,
-                              uint8_t *q, float *scales, hipStream_t s) {
+                              uint8_t *q, float *scales, hipStream_t s,
+                              uint32_t *zero = nullptr, int64_t nzero = 0,
+                              bool *cleared = nullptr) {
   const bool vec = ld % 4 == 0 && ((uintptr_t)P & 15) == 0;
+  const int chw = (int)((Kp + 255) / 256);
+  const int64_t threads = 256 * (chw <= 2 ? (R + 3) / 4 : R);
+  if (zero == nullptr || nzero > threads) nzero = 0;
+  if (cleared) *cleared = nzero > 0;
   // Short rows (at most 512 padded elements): one wave per row.  Measured on
   // 4096-row operands, 7 % faster than a workgroup per row at K = 300 and
   // 16 % slower at K = 4096, where four rows per workgroup keep too few bytes
   // in flight per CU.
-  const int chw = (int)((Kp + 255) / 256);
   if (chw <= 2) {
     const unsigned grid = (unsigned)((R + 3) / 4);
 #define MM_QWAVE(CH)                                                                               \
   do {                                                                                             \
     if (vec)                                                                                       \
       hipLaunchKernelGGL((fp8::quant_rows_wave_kernel<CH, true>), dim3(grid), dim3(256), 0, s,      \
-                         (int)R, (int)K, Kp, P, ld, q, scales);                                    \
+                         (int)R, (int)K, Kp, P, ld, q, scales, zero, nzero);                       \
     else                                                                                           \
       hipLaunchKernelGGL((fp8::quant_rows_wave_kernel<CH, false>), dim3(grid), dim3(256), 0, s,     \
-                         (int)R, (int)K, Kp, P, ld, q, scales);                                    \
+                         (int)R, (int)K, Kp, P, ld, q, scales, zero, nzero);                       \
   } while (0)
     if (chw == 1) MM_QWAVE(1);
     else MM_QWAVE(2);
@@ -710,10 +734,10 @@ static gemm_status quant_rows(int64_t R, int64_t K, int64_t Kp, const float *P, 
   do {                                                                                           \
     if (vec)                                                                                     \
       hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, true>), dim3((unsigned)R), dim3(256), 0, \
-                         s, (int)R, (int)K, Kp, P, ld, q, scales);                               \
+                         s, (int)R, (int)K, Kp, P, ld, q, scales, zero, nzero);                  \
     else                                                                                         \
       hipLaunchKernelGGL((fp8::quant_rows_reg_kernel<CH, false>), dim3((unsigned)R), dim3(256),  \
-                         0, s, (int)R, (int)K, Kp, P, ld, q, scales);                            \
+                         0, s, (int)R, (int)K, Kp, P, ld, q, scales, zero, nzero);               \
   } while (0)
   switch (ch) {
     case 1: MM_QROWS(1); break;
@@ -726,7 +750,7 @@ static gemm_status quant_rows(int64_t R, int64_t K, int64_t Kp, const float *P, 
     case 8: MM_QROWS(8); break;
     default:
       hipLaunchKernelGGL(fp8::quant_rows_kernel, dim3((unsigned)R), dim3(256), 0, s, (int)R,
-                         (int)K, Kp, P, ld, q, scales);
+                         (int)K, Kp, P, ld, q, scales, zero, nzero);
   }
 #undef MM_QROWS
   return check_launch("quant_rows_kernel");
@@ -734,12 +758,15 @@ static gemm_status quant_rows(int64_t R, int64_t K, int64_t Kp, const float *P, 
 
 // Column quantisation: a K x Nc matrix (row stride ld) -> per-column scales
 // and the codes of each column in a row of Kp bytes (transposed, k
-// contiguous).  amax: Nc words of scratch.
+// contiguous).  amax: Nc words of scratch, already zero when amax_clear.
 static gemm_status quant_cols(int64_t K, int64_t Nc, int64_t Kp, const float *P, int64_t ld,
-                              uint32_t *amax, uint8_t *q, float *scales, hipStream_t s) {
-  const unsigned fg = (unsigned)std::min<int64_t>((Nc + 255) / 256, 1024);
-  hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, Nc);
-  if (gemm_status st = check_launch("fill_u32_kernel")) return st;
+                              uint32_t *amax, uint8_t *q, float *scales, hipStream_t s,
+                              bool amax_clear = false) {
+  if (!amax_clear) {
+    const unsigned fg = (unsigned)std::min<int64_t>((Nc + 255) / 256, 1024);
+    hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, Nc);
+    if (gemm_status st = check_launch("fill_u32_kernel")) return st;
+  }
   const bool vec = ld % 4 == 0 && ((uintptr_t)P & 15) == 0;
   const dim3 ag((unsigned)((Nc + 63) / 64), (unsigned)std::max<int64_t>(1, (K + 255) / 256));
   if (vec)
@@ -765,14 +792,17 @@ gemm_status fp8_quantize_run(int64_t M, int64_t N, int64_t K, const float *A, in
   float *sa = reinterpret_cast<float *>(base + L.sa);
   float *sb = reinterpret_cast<float *>(base + L.sb);
   uint32_t *amax = reinterpret_cast<uint32_t *>(base + L.amax);
+  // When A goes by rows and B by columns, A's launch clears B's amax words.
+  bool amax_clear = false;
   if (M > 0) {
     gemm_status st = ta ? quant_cols(K, M, L.Kp, A, lda, amax, qa, sa, s)
-                        : quant_rows(M, K, L.Kp, A, lda, qa, sa, s);
+                        : quant_rows(M, K, L.Kp, A, lda, qa, sa, s, (N > 0 && !tb) ? amax : nullptr,
+                                     N, &amax_clear);
     if (st) return st;
   }
   if (N > 0) {
     gemm_status st = tb ? quant_rows(N, K, L.Kp, B, ldb, qb, sb, s)
-                        : quant_cols(K, N, L.Kp, B, ldb, amax, qb, sb, s);
+                        : quant_cols(K, N, L.Kp, B, ldb, amax, qb, sb, s, amax_clear);
     if (st) return st;
   }
   return GEMM_STATUS_OK;

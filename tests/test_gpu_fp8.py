@@ -109,6 +109,34 @@ def test_quantiser_special_values_are_bitwise_the_oracle(M, N, K):
     assert not qa[:, K:].any() and not qbT[:, K:].any()
 
 
+@pytest.mark.parametrize("M,N,K", [(300, 260, 1000), (40, 700, 300), (3, 2000, 64)])
+def test_quantiser_reused_workspace(M, N, K):
+    """Two quantisations into one workspace, the second with values 1e6 times
+    smaller: the column maxima of the first must not survive into the second
+    (the column scratch is cleared by the row launch of A, or by its own
+    launch when A's grid is too small: M = 3, N = 2000)."""
+    import torch
+    import paper_1902_10345_amd as mm
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    g = np.random.default_rng(M + N)
+    L = mm.fp8_workspace_layout(M, N, K)
+    for scale in (1e3, 1e-3):
+        A = (g.standard_normal((M, K)) * scale).astype(np.float32)
+        B = (g.standard_normal((K, N)) * scale).astype(np.float32)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        mm.fp8_quantize(M, N, K, dA, K, dB, N, ws, nbytes)
+        torch.cuda.synchronize()
+        h = ws.cpu().numpy()
+        Kp = L["Kp"]
+        sa = h[L["sa"]:L["sa"] + 4 * M].view(np.float32)
+        sb = h[L["sb"]:L["sb"] + 4 * N].view(np.float32)
+        qbT = h[L["qb"]:L["qb"] + N * Kp].reshape(N, Kp)
+        rsa, rsb = oracle.fp8_scales_rows(A), oracle.fp8_scales_cols(B)
+        assert np.array_equal(sa, rsa) and np.array_equal(sb, rsb)
+        assert np.array_equal(qbT[:, :K].T, oracle.fp8_quantize_cols(B, rsb))
+
+
 # The matrix core's internal summation of one 64-deep FP8 block is not
 # specified to IEEE sequential-rounding accuracy; componentwise errors of up to
 # 2.4 gamma_K against the dequantised oracle were measured, so the pin allows 8.
