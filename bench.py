@@ -160,7 +160,9 @@ def run_grouped(torch, mm, steps, warmup):
     tf = flops / (ms * 1e-3) / 1e12
     gbs = min_bytes / (ms * 1e-3) / 1e9
     n128 = int(sum(1 for v in variants if v == 0))
-    return {"problems": len(dev), "gflop": round(flops / 1e9, 3),
+    torch.cuda.synchronize()
+    outputs = [d[7].cpu().numpy() for d in dev]   # the last replay's results
+    return probs, outputs, {"problems": len(dev), "gflop": round(flops / 1e9, 3),
             "min_hbm_mb": round(min_bytes / 1e6, 1), "ms": round(ms, 4),
             "tflops": round(tf, 1), "frac_3product_ceiling": round(tf * 3 / PEAK_BF16_MFMA, 4),
             "hbm_gbs_of_min_bytes": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
@@ -182,9 +184,11 @@ def run_serving(torch, mm, seconds, rate=2000.0):
     budget = 16 << 30
     arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
     srv = mm.server_create(arena, budget, 1024, mm.PATH_3XBF16, 4)
-    outstanding = collections.deque()                 # (ticket, ring_off, n)
+    outstanding = collections.deque()                 # (ticket, ring_off, n, index)
     head = 0
     lat = []
+    sample_every = 100                                # every 100th request is kept
+    kept = {}                                         # index -> result copy
 
     def reap():
         """Collect completed requests in submission order."""
@@ -193,7 +197,9 @@ def run_serving(torch, mm, seconds, rate=2000.0):
             if r is None:
                 return
             lat.append(r)
-            outstanding.popleft()
+            _, off, n, idx = outstanding.popleft()
+            if idx % sample_every == 0:
+                kept[idx] = ring[off:off + n].numpy().copy()
 
     def overlaps_oldest(lo, hi):
         return bool(outstanding) and outstanding[0][1] < hi and outstanding[0][1] + outstanding[0][2] > lo
@@ -221,7 +227,7 @@ def run_serving(torch, mm, seconds, rate=2000.0):
             hB = pool[offB:offB + K * N]
             hC = ring[head:head + n]
             t = mm.server_submit(srv, M, N, K, 1.0, hA, hB, 0.0, None, hC, due)
-            outstanding.append((t, head, n))
+            outstanding.append((t, head, n, i))
             head += n
             if i % 8 == 0:
                 reap()
@@ -232,12 +238,23 @@ def run_serving(torch, mm, seconds, rate=2000.0):
         mm.server_destroy(srv)
     del arena
     offered = sum(2.0 * float(m) * float(n_) * float(k) for (m, n_, k) in sizes) / seconds
-    return {"rate_req_s": rate, "seconds": seconds, "requests": int(len(t_arr)),
+    # the kept 1 % sample, with the operands each request read from the pool
+    sample = []
+    for idx in sorted(kept):
+        M, N, K = (int(v) for v in sizes[idx])
+        offA = (idx * 2654435761) % (pool_n - M * K)
+        offB = (idx * 40503 + 12345) % (pool_n - K * N)
+        A = pool[offA:offA + M * K].numpy().reshape(M, K)
+        B = pool[offB:offB + K * N].numpy().reshape(K, N)
+        sample.append((A, B, kept[idx].reshape(M, N)))
+    return sample, {"rate_req_s": rate, "seconds": seconds, "requests": int(len(t_arr)),
             "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
             "result_p50_ms": round(st["result_p50_ms"], 4),
             "result_p99_ms": round(st["result_p99_ms"], 4),
             "tflops": round(st["tflops"], 3), "offered_tflops": round(offered / 1e12, 3),
-            "completed": st["completed"], "max_in_flight": st["max_in_flight"],
+            "completed": st["completed"], "failed": st["failed"],
+            "max_in_flight": st["max_in_flight"],
+            "max_concurrent_steps": st["max_concurrent_steps"],
             "arena_high_water_mb": round(st["arena_high_water_bytes"] / 1e6, 1),
             "budget_gb": budget / (1 << 30), "streams": 4, "slots": 1024}
 
@@ -247,18 +264,23 @@ def run_profile(torch, mm):
     byte counters), for rocprofv3 counter runs."""
     M = N = K = 4096
     _, (A, B, C) = _dev_inputs(M, N, K, 2, torch)
+    valu = [c for c in range(mm.gemm_num_configs(mm.PATH_F32))
+            if mm.gemm_config_name(mm.PATH_F32, c) == "f32_128x128x32_r8x8_u2"][0]
     for i in range(5):
         mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, C, N, 3)
         mm.gemm_f32(M, N, K, 1.5, A, K, B, N, 0.5, C, N)
+        mm.gemm_run_config(mm.PATH_F32, valu, M, N, K, 1.5, A, K, B, N, 0.5, C, N)
     nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    An, Bn = torch.randn(M, K, device="cuda"), torch.randn(K, N, device="cuda")
+    import seeded_inputs as si
+    fA, fB, _ = si.fp8_workload(M, N, K, seed=4, outliers="A")
+    An, Bn = torch.from_numpy(fA).cuda(), torch.from_numpy(fB).cuda()
+    del fA, fB
     for i in range(5):
         mm.fp8_quantize(M, N, K, An, K, Bn, N, ws, nbytes)
     for i in range(5):
         mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, C, N)
     del An, Bn, ws
-    import seeded_inputs as si
     dev = []
     for (Mg, Ng, Kg, Ag, Bg) in si.grouped_problems(512, seed=5):
         dC = torch.empty((Mg, Ng), dtype=torch.float32, device="cuda")
@@ -286,9 +308,153 @@ def run_profile(torch, mm):
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    _log("profile run done: 5 x gemm_bx3, gemm_f32, fp8_quantize, gemm_fp8, gemm_f64 (4096^3), "
+    _log("profile run done: 5 x gemm_bx3, gemm_f32 (matrix cores and the vector-ALU tile), "
+         "fp8_quantize, gemm_fp8, gemm_f64 (4096^3), "
          "5 x grouped 512, "
          "5 x batched 32^3 x 29297 (binary64), 5 x copy of 1 GiB")
+
+
+def _threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+
+
+def _err(oracle, C, ref, den):
+    rel, _, _, cw = oracle.norms(C, ref, den)
+    return {"rel_fro": float("%.4g" % rel), "componentwise_max": float("%.4g" % cw)}
+
+
+def run_accuracy(torch, mm, head_inputs, grouped_run, serving_sample):
+    """Each path's error against the binary64 oracle over the whole result:
+    relative Frobenius and componentwise max |dC| / (|alpha||A||B| +
+    |beta||C0|).  The oracle runs on all host threads; its times are the CPU
+    baseline (the whole 4096^3 headline product) and the per-workload
+    detail (all threads, and one thread on a row sample)."""
+    import numpy as np
+    import oracle
+    import seeded_inputs as si
+    T = _threads()
+    acc, detail = {}, {"threads": T}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return r, time.perf_counter() - t0
+
+    def one_thread(A, B, C0, alpha, beta, rows):
+        sel = np.linspace(0, A.shape[0] - 1, rows).astype(np.int64)
+        _, dt = timed(lambda: oracle.gemm(A[sel], B, alpha=alpha, beta=beta,
+                                          C0=None if C0 is None else C0[sel], nthreads=1))
+        return {"rows": rows, "s": round(dt, 3),
+                "gflops": round(2.0 * rows * A.shape[1] * B.shape[1] / dt / 1e9, 3)}
+
+    def dense(tag, M, N, K, seed, alpha, beta, runs, hin=None):
+        if hin is None:
+            hin = (si.uniform((M, K), seed), si.uniform((K, N), seed + 100),
+                   si.uniform((M, N), seed + 200))
+        A, B, C0 = hin
+        _log("accuracy: oracle %s (%d threads)" % (tag, T))
+        ref, dt = timed(lambda: oracle.gemm(A, B, alpha=alpha, beta=beta, C0=C0, nthreads=T))
+        den = oracle.gemm_abs(A, B, alpha=alpha, beta=beta, C0=C0, nthreads=T)
+        detail[tag] = {"all_threads_s": round(dt, 3),
+                       "all_threads_gflops": round(2.0 * M * N * K / dt / 1e9, 2),
+                       "one_thread": one_thread(A, B, C0, alpha, beta, min(M, 64))}
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        for name, call in runs:
+            dC = torch.from_numpy(C0).cuda()
+            call(dA, dB, dC)
+            torch.cuda.synchronize()
+            acc[name] = _err(oracle, dC.cpu().numpy(), ref, den)
+        return dt
+
+    valu = [c for c in range(mm.gemm_num_configs(mm.PATH_F32))
+            if mm.gemm_config_name(mm.PATH_F32, c) == "f32_128x128x32_r8x8_u2"][0]
+
+    def runs_for(tag, M, N, K, alpha, beta, valu_too):
+        r = [("3xbf16_n3_" + tag, lambda a, b, c: mm.gemm_f32_3xbf16(M, N, K, alpha, a, K, b, N,
+                                                                     beta, c, N, 3)),
+             ("3xbf16_n6_" + tag, lambda a, b, c: mm.gemm_f32_3xbf16(M, N, K, alpha, a, K, b, N,
+                                                                     beta, c, N, 6)),
+             ("f32_" + tag, lambda a, b, c: mm.gemm_f32(M, N, K, alpha, a, K, b, N, beta, c, N))]
+        if valu_too:
+            r.append(("f32_valu_" + tag, lambda a, b, c: mm.gemm_run_config(
+                mm.PATH_F32, valu, M, N, K, alpha, a, K, b, N, beta, c, N)))
+        return r
+
+    t_head = dense("4096^3", 4096, 4096, 4096, 2, 1.5, 0.5,
+                   runs_for("4096^3", 4096, 4096, 4096, 1.5, 0.5, True), head_inputs)
+    dense("8192x2048x4096", 8192, 2048, 4096, 3, 1.5, 0.5,
+          runs_for("8192x2048x4096", 8192, 2048, 4096, 1.5, 0.5, True))
+    dense("256^3", 256, 256, 256, 1, 1.0, 0.0, runs_for("256^3", 256, 256, 256, 1.0, 0.0, False))
+    cpu = {"value": round(2.0 * 4096 ** 3 / t_head / 1e12, 6), "unit": "TFLOP/s", "cores": T,
+           "kind": "oracle",
+           "sample": "the whole 4096^3 headline product (alpha=1.5, beta=0.5), FP64 i-k-j "
+                     "loop over all rows, %.1f s on %d threads" % (t_head, T)}
+
+    # FP8 at 4096^3 for the three outlier variants: against the dequantised
+    # oracle (codes and scales read back) and against the exact product
+    M = N = K = 4096
+    nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    L = mm.fp8_workspace_layout(M, N, K)
+    for outl in ("none", "A", "B"):
+        A, B, C0 = si.fp8_workload(M, N, K, seed=4, outliers=outl)
+        dA, dB, dC = (torch.from_numpy(x).cuda() for x in (A, B, C0))
+        mm.gemm_fp8_scaled(M, N, K, 1.5, dA, K, dB, N, 0.5, dC, N, ws, nbytes)
+        torch.cuda.synchronize()
+        C = dC.cpu().numpy()
+        h = ws.cpu().numpy()
+        Kp = L["Kp"]
+        qa = np.ascontiguousarray(h[L["qa"]:L["qa"] + M * Kp].reshape(M, Kp)[:, :K])
+        qb = np.ascontiguousarray(h[L["qb"]:L["qb"] + N * Kp].reshape(N, Kp)[:, :K].T)
+        sa = h[L["sa"]:L["sa"] + 4 * M].view(np.float32).copy()
+        sb = h[L["sb"]:L["sb"] + 4 * N].view(np.float32).copy()
+        _log("accuracy: oracle fp8 outliers=%s" % outl)
+        refq, dtq = timed(lambda: oracle.gemm_fp8_dequant(qa, sa, qb, sb, alpha=1.5, beta=0.5,
+                                                          C0=C0, nthreads=T))
+        denq = oracle.gemm_fp8_dequant(qa & 0x7F, sa, qb & 0x7F, sb, alpha=1.5, beta=0.5,
+                                       C0=np.abs(C0), nthreads=T)
+        ref = oracle.gemm(A, B, alpha=1.5, beta=0.5, C0=C0, nthreads=T)
+        den = oracle.gemm_abs(A, B, alpha=1.5, beta=0.5, C0=C0, nthreads=T)
+        acc["fp8_4096^3_outliers_" + outl] = {"vs_exact": _err(oracle, C, ref, den),
+                                              "vs_dequantised": _err(oracle, C, refq, denq)}
+        if outl == "A":
+            detail["fp8_dequant_4096^3"] = {"all_threads_s": round(dtq, 3)}
+        del A, B, C0, dA, dB, dC, refq, denq, ref, den
+    del ws
+
+    if grouped_run is not None:
+        probs, outputs = grouped_run
+        _log("accuracy: oracle on all 512 grouped problems")
+        worst_rel = worst_cw = 0.0
+        t0 = time.perf_counter()
+        for (Mg, Ng, Kg, A, B), C in zip(probs, outputs):
+            ref = oracle.gemm(A, B, nthreads=T)
+            den = oracle.gemm_abs(A, B, nthreads=T)
+            rel, _, _, cw = oracle.norms(C, ref, den)
+            worst_rel, worst_cw = max(worst_rel, rel), max(worst_cw, cw)
+        acc["grouped_512_max_over_members"] = {"rel_fro": float("%.4g" % worst_rel),
+                                               "componentwise_max": float("%.4g" % worst_cw)}
+        gfl = sum(2.0 * p[0] * p[1] * p[2] for p in probs) / 1e9
+        detail["grouped_512_all_problems"] = {
+            "s_including_abs_pass": round(time.perf_counter() - t0, 3), "gflop": round(gfl, 2)}
+
+    if serving_sample:
+        _log("accuracy: oracle on the %d-request serving sample" % len(serving_sample))
+        worst_rel = worst_cw = 0.0
+        t0 = time.perf_counter()
+        fl = 0.0
+        for (A, B, C) in serving_sample:
+            ref = oracle.gemm(A, B, nthreads=T)
+            fl += 2.0 * A.shape[0] * A.shape[1] * B.shape[1]
+            den = oracle.gemm_abs(A, B, nthreads=T)
+            rel, _, _, cw = oracle.norms(C, ref, den)
+            worst_rel, worst_cw = max(worst_rel, rel), max(worst_cw, cw)
+        acc["serving_1pct_sample_max"] = {"requests": len(serving_sample),
+                                          "rel_fro": float("%.4g" % worst_rel),
+                                          "componentwise_max": float("%.4g" % worst_cw)}
+        detail["serving_1pct_sample"] = {"s_including_abs_pass": round(time.perf_counter() - t0, 3),
+                                         "gflop": round(fl / 1e9, 2)}
+    return cpu, detail, acc
 
 
 def main():
@@ -372,8 +538,10 @@ def main():
             flops, PEAK_FP32_VALU, "fp32_peak")
         nbytes = mm.gemm_fp8_workspace_bytes(M, N, K)
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        An = torch.randn(M, K, device="cuda")
-        Bn = torch.randn(K, N, device="cuda")
+        import seeded_inputs as si
+        fA, fB, _ = si.fp8_workload(M, N, K, seed=4, outliers="A")
+        An, Bn = torch.from_numpy(fA).cuda(), torch.from_numpy(fB).cuda()
+        del fA, fB
         one("fp8_scaled_4096^3_with_quantize",
             lambda: mm.gemm_fp8_scaled(M, N, K, 1.5, An, K, Bn, N, 0.5, Cf, N, ws, nbytes),
             flops, PEAK_FP8_MFMA, "fp8_peak")
@@ -459,42 +627,20 @@ def main():
             2.0 * M6 * N * K, PEAK_BF16_MFMA, "bf16_peak")
         del A6, B6, C6, ws5, ws6
 
-    grouped = None
+    grouped = grouped_run = None
     if not args.no_grouped:
         _log("grouped: 512 problems, autotuned tiles, graph replay")
-        grouped = run_grouped(torch, mm, K_, W_)
-    serving = None
+        *grouped_run, grouped = run_grouped(torch, mm, K_, W_)
+    serving = serving_sample = None
     if not args.no_serving:
         _log("serving: Poisson 2000 req/s for %.0f s" % args.serve_seconds)
-        serving = run_serving(torch, mm, args.serve_seconds)
+        serving_sample, serving = run_serving(torch, mm, args.serve_seconds)
 
-    # ---------------- CPU baseline: the oracle on a bounded sample ----------
-    cpu = None
-    accuracy = None
+    # ---------------- accuracy of every path and the CPU baseline -----------
+    cpu = cpu_detail = accuracy = None
     if not args.no_cpu_baseline:
-        import numpy as np
-        import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-        # re-run the headline GEMM once from the original C0 for the accuracy check
-        Cchk = torch.from_numpy(hC0).cuda()
-        mm.gemm_f32_3xbf16(M, N, K, 1.5, A, K, B, N, 0.5, Cchk, N, 3)
-        torch.cuda.synchronize()
-        # size the sample for about 15 s of CPU work from a 32-row probe
-        t0 = time.perf_counter()
-        oracle.gemm(hA[:32], hB, alpha=1.5, beta=0.5, C0=hC0[:32], nthreads=threads)
-        t32 = time.perf_counter() - t0
-        rows = int(min(M, max(32, 32 * 15.0 / max(t32, 1e-3))) // 32 * 32)
-        _log("cpu_baseline: oracle on %d rows of the 4096^3 product, %d threads" % (rows, threads))
-        sel = np.linspace(0, M - 1, rows).astype(np.int64)
-        t0 = time.perf_counter()
-        ref = oracle.gemm(hA[sel], hB, alpha=1.5, beta=0.5, C0=hC0[sel], nthreads=threads)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(2.0 * rows * N * K / dt / 1e12, 6), "unit": "TFLOP/s",
-               "cores": threads, "kind": "oracle",
-               "sample": "%d of %d evenly spaced rows of the 4096^3 product (alpha=1.5, "
-                         "beta=0.5), FP64 i-k-j loop, %.1f s" % (rows, M, dt)}
-        accuracy = {"3xbf16_n3_rel_fro_sampled_rows": oracle.rel_fro(Cchk.cpu().numpy()[sel], ref)}
-
+        cpu, cpu_detail, accuracy = run_accuracy(torch, mm, (hA, hB, hC0), grouped_run,
+                                                 serving_sample)
     achieved = head_tflops
     line = {
         "metric": "FP32-accurate GEMM TFLOP/s & % peak: plain vs 3xBF16 MFMA; serve p50/p99 ms",
@@ -507,7 +653,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "3xbf16 (bf16 split products, f32 accumulate)",
         "data": "synthetic",
         "config": {"workload": "gemm 4096x4096x4096 fp32 row-major, alpha=1.5 beta=0.5, "
                                "FP32-accurate via 3 bf16 split products on MFMA (fp32 accumulate)",
@@ -521,6 +667,7 @@ def main():
         "grouped": grouped,
         "serving": serving,
         "accuracy": accuracy,
+        "cpu_baseline_detail": cpu_detail,
         "wall_s_timed_region": round(wall, 3),
         "settle_s_before_warmup": args.settle_seconds,
         "sclk_dpm_mhz_after_timed": sclk,

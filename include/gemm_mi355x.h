@@ -52,6 +52,8 @@ typedef int gemm_status;
 #define GEMM_STATUS_UNSUPPORTED   4  /* e.g. device is not gfx950 */
 #define GEMM_STATUS_REJECTED      5  /* server: request can never fit the budget */
 #define GEMM_STATUS_UNKNOWN       6  /* server: unknown ticket */
+#define GEMM_STATUS_CANCELLED     7  /* server: request cancelled before admission */
+#define GEMM_STATUS_TIMED_OUT     8  /* server: request waited longer than the queue timeout */
 
 /* Thread-local text of the last failure on this thread ("" if none). */
 const char *gemm_last_error(void);
@@ -60,13 +62,17 @@ const char *gemm_last_error(void);
 const char *gemm_version(void);
 
 /* ------------------------------------------------------------------------
- * Plain FP32 path (vector ALU).
- * C <- alpha*A*B + beta*C with binary32 fused multiply-add accumulation in
- * registers.  Tiling of the (i,j) map, LDS staging of A/B tiles with double
- * buffering and per-lane register micro-tiles realise the MapTiling,
- * LocalStorage, DoubleBuffering and Vectorization steps of the paper's
- * transformation chain (Sec. 6.2, App. B table of transformations); alpha and
- * beta are applied once in a peeled epilogue (ReducePeeling, Sec. 6.2).
+ * Plain FP32 path: binary32 products and binary32 sums, no split.
+ * C <- alpha*A*B + beta*C.  The library picks the tile configuration per
+ * shape (gemm_default_config): where its tiles fill the compute units the
+ * binary32 matrix-core tile (v_mfma_f32_32x32x2_f32: each product and sum in
+ * binary32), otherwise a vector-ALU tile with fused multiply-add accumulation
+ * in per-lane register micro-tiles; gemm_run_config selects either kind.
+ * Tiling of the (i,j) map, LDS staging of A/B tiles with double buffering and
+ * register micro-tiles realise the MapTiling, LocalStorage, DoubleBuffering
+ * and Vectorization steps of the paper's transformation chain (Sec. 6.2,
+ * App. B table of transformations); alpha and beta are applied once in a
+ * peeled epilogue (ReducePeeling, Sec. 6.2).
  * Arguments: 1 M, 2 N, 3 K, 4 alpha, 5 A, 6 lda, 7 B, 8 ldb, 9 beta, 10 C,
  * 11 ldc, 12 stream.
  * ---------------------------------------------------------------------- */
@@ -356,8 +362,26 @@ gemm_status grouped_graph_destroy(void *graph);
  * 6 out.  server_submit arguments: 1 server, 2 M, 3 N, 4 K, 5 alpha, 6 hA,
  * 7 hB, 8 beta, 9 hC0 (read when beta != 0), 10 hC_out, 11 arrival (seconds on
  * the server clock, or < 0), 12 ticket (out).  A request larger than the whole
- * arena returns GEMM_STATUS_REJECTED.  server_poll returns GEMM_STATUS_NOT_READY
- * until the result is in hC_out, then the latencies (and forgets the ticket).
+ * arena returns GEMM_STATUS_REJECTED; one whose K or N exceeds the grouped
+ * kernel's 32-bit tile offsets ((129 K) * 4 or (33 N) * 4 bytes >= 2^31)
+ * returns GEMM_STATUS_UNSUPPORTED; both count as rejected.  server_poll
+ * returns GEMM_STATUS_NOT_READY until the result is in hC_out, then the
+ * latencies (and forgets the ticket).  A request that ended without a result
+ * is reported once by server_poll with its status and then forgotten:
+ * GEMM_STATUS_HIP_ERROR (its step's copies or launch could not be enqueued,
+ * or the device reported an error; hC_out holds no result),
+ * GEMM_STATUS_CANCELLED or GEMM_STATUS_TIMED_OUT.  After a device error
+ * reported asynchronously the server is failed: server_submit and
+ * server_drain return GEMM_STATUS_HIP_ERROR.  For tests of the error path the
+ * environment variable GEMM_SERVER_INJECT_STEP_FAILURES=n, read by
+ * server_create, makes the first n steps fail before anything is enqueued.
+ *
+ * server_cancel removes a request that is still queued (not yet admitted);
+ * its poll then returns GEMM_STATUS_CANCELLED.  An admitted request cannot be
+ * cancelled (GEMM_STATUS_NOT_READY: it completes normally).  Arguments:
+ * 1 server, 2 ticket.  server_set_queue_timeout drops queued requests that
+ * waited longer than `seconds` since their arrival stamp without being
+ * admitted (0, the default, waits forever).  Arguments: 1 server, 2 seconds.
  * ---------------------------------------------------------------------- */
 typedef struct gemm_server gemm_server;
 gemm_status server_create(void *arena, size_t arena_bytes, int max_slots, int path,
@@ -371,11 +395,18 @@ gemm_status server_poll(gemm_server *server, uint64_t ticket, double *latency_ms
 /* Blocks until every submitted request has completed (or timeout_s passes:
  * GEMM_STATUS_NOT_READY). */
 gemm_status server_drain(gemm_server *server, double timeout_s);
+gemm_status server_cancel(gemm_server *server, uint64_t ticket);
+gemm_status server_set_queue_timeout(gemm_server *server, double seconds);
 /* Latency percentiles over completed requests, throughput (completed
- * algorithmic flops over first arrival .. last completion), counters. */
+ * algorithmic flops over first arrival .. last completion), counters:
+ * max_in_flight (admitted requests at once), arena_high_water (bytes),
+ * rejected (at submit), failed (ended with GEMM_STATUS_HIP_ERROR) and
+ * max_concurrent_steps (steps enqueued on different streams and not yet
+ * complete at once).  Every output pointer may be NULL. */
 gemm_status server_stats(gemm_server *server, double *p50_ms, double *p99_ms, double *tflops,
                          uint64_t *completed, double *result_p50_ms, double *result_p99_ms,
-                         int *max_in_flight, size_t *arena_high_water, uint64_t *rejected);
+                         int *max_in_flight, size_t *arena_high_water, uint64_t *rejected,
+                         uint64_t *failed, int *max_concurrent_steps);
 gemm_status server_destroy(gemm_server *server);
 
 /* ------------------------------------------------------------------------
@@ -390,10 +421,12 @@ gemm_status server_destroy(gemm_server *server);
  * 14 workspace, 15 ws_bytes (FP8), 16 reps, 17 stream, 18 best_cfg (out).
  *
  * grouped_autotune times candidate tile-shape policies for a grouped batch
- * (all 128 x 128, all 64 x 64, and the padded-work rule at several costs of
- * the small tile) and writes the fastest per-problem variants to
- * variants_out (count ints); later library choices for grouped batches use
- * the winning rule.  Arguments: 1 problems, 2 count, 3 path, 4 workspace,
+ * (the padded-work rule at several relative costs of a 64 x 64 tile element,
+ * including 0 -- every problem on 64 x 64 tiles -- and a cost so large that
+ * every problem takes 128 x 128 tiles) and writes the fastest per-problem
+ * variants to variants_out (count ints); the winning rule becomes the
+ * library's, so grouped_default_variant and grouped calls without explicit
+ * variants reproduce variants_out for these problems.  Arguments: 1 problems, 2 count, 3 path, 4 workspace,
  * 5 ws_bytes, 6 reps, 7 stream, 8 variants_out.
  *
  * gemm_tuner_save / gemm_tuner_load write and read the tuned table as JSON.

@@ -23,6 +23,8 @@ STATUS_NOT_READY = 3
 STATUS_UNSUPPORTED = 4
 STATUS_REJECTED = 5
 STATUS_UNKNOWN = 6
+STATUS_CANCELLED = 7
+STATUS_TIMED_OUT = 8
 
 
 class GemmError(RuntimeError):
@@ -105,7 +107,10 @@ _sig("server_poll", _int, _vp, ctypes.c_uint64, ctypes.POINTER(_dbl), ctypes.POI
 _sig("server_drain", _int, _vp, _dbl)
 _sig("server_stats", _int, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
-     ctypes.POINTER(_int), ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_uint64))
+     ctypes.POINTER(_int), ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_uint64),
+     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_int))
+_sig("server_cancel", _int, _vp, ctypes.c_uint64)
+_sig("server_set_queue_timeout", _int, _vp, _dbl)
 _sig("server_destroy", _int, _vp)
 _sig("gemm_autotune", _int, _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64,
      _int, _vp, _sz, _int, _vp, ctypes.POINTER(_int))
@@ -312,18 +317,29 @@ def server_drain(server, timeout_s=60.0):
     return check(lib.server_drain(server, timeout_s))
 
 
+def server_cancel(server, ticket):
+    """Cancel a request that is still queued (GemmError with STATUS_NOT_READY
+    once it has been admitted)."""
+    return check(lib.server_cancel(server, ticket))
+
+
+def server_set_queue_timeout(server, seconds):
+    return check(lib.server_set_queue_timeout(server, float(seconds)))
+
+
 def server_stats(server) -> dict:
     p50, p99, tf, rp50, rp99 = _dbl(), _dbl(), _dbl(), _dbl(), _dbl()
-    done, rej = ctypes.c_uint64(), ctypes.c_uint64()
-    mif = _int()
+    done, rej, fail = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    mif, mcs = _int(), _int()
     hw = _sz()
     check(lib.server_stats(server, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(tf),
                            ctypes.byref(done), ctypes.byref(rp50), ctypes.byref(rp99),
-                           ctypes.byref(mif), ctypes.byref(hw), ctypes.byref(rej)))
+                           ctypes.byref(mif), ctypes.byref(hw), ctypes.byref(rej),
+                           ctypes.byref(fail), ctypes.byref(mcs)))
     return {"p50_ms": p50.value, "p99_ms": p99.value, "tflops": tf.value,
             "completed": done.value, "result_p50_ms": rp50.value, "result_p99_ms": rp99.value,
             "max_in_flight": mif.value, "arena_high_water_bytes": hw.value,
-            "rejected": rej.value}
+            "rejected": rej.value, "failed": fail.value, "max_concurrent_steps": mcs.value}
 
 
 def server_destroy(server):

@@ -3,9 +3,9 @@
 //
 // The batch is flattened into one list of output tiles (problem p owns tiles
 // [start[p], start[p+1])).  A grid sized to the machine's resident capacity
-// pulls tile indices from an atomic counter -- the batch-dequeue mechanism the
-// paper uses to implement consume scopes (Sec. 3.3, "Consume" scopes are
-// implemented with batch stream dequeue and atomic operations) -- finds the
+// takes tile indices from an atomic counter -- the mechanism behind the
+// paper's consume scopes (Sec. 3.3), where workers take elements off a shared
+// stream with atomic operations -- finds the
 // owning problem by binary search over the prefix of tile counts and runs the
 // same tile body as the single-GEMM kernel.  Each problem carries its own tile
 // shape, chosen per problem (library heuristic or the autotuner).

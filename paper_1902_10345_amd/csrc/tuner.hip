@@ -84,9 +84,13 @@ gemm_status gemm_autotune(int path, int64_t M, int64_t N, int64_t K, float alpha
   if (path < GEMM_PATH_F32 || path > GEMM_PATH_FP8_PREQUANTIZED) return bad_arg(1, fn, "(path) unknown");
   if (reps < 1) return bad_arg(16, fn, "(reps) must be >= 1");
   if (!best_cfg) return bad_arg(18, fn, "(best_cfg) is NULL");
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return hip_fail(fn, hipGetLastError());
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return hip_fail("gemm_autotune: event", he);
+  }
   int best = -1;
   float best_ms = 0.0f;
   gemm_status last = GEMM_STATUS_OK;
@@ -96,14 +100,19 @@ gemm_status gemm_autotune(int path, int64_t M, int64_t N, int64_t K, float alpha
                                      n_products, workspace, ws_bytes, stream);
     if (st < 0) { hipEventDestroy(e0); hipEventDestroy(e1); return st; }  // bad arguments
     if (st) { last = st; continue; }                                      // config unusable here
-    hipEventRecord(e0, stream);
-    for (int r = 0; r < reps; ++r)
-      gemm_run_config(path, c, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products,
-                      workspace, ws_bytes, stream);
-    hipEventRecord(e1, stream);
-    hipEventSynchronize(e1);
+    he = hipEventRecord(e0, stream);
+    for (int r = 0; !st && he == hipSuccess && r < reps; ++r)
+      st = gemm_run_config(path, c, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products,
+                           workspace, ws_bytes, stream);
+    if (!st && he == hipSuccess) he = hipEventRecord(e1, stream);
+    if (!st && he == hipSuccess) he = hipEventSynchronize(e1);
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, e0, e1);
+    if (!st && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (st || he != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return st ? st : hip_fail("gemm_autotune: timing", he);
+    }
     if (best < 0 || ms < best_ms) { best = c; best_ms = ms; }
   }
   hipEventDestroy(e0);
@@ -134,21 +143,26 @@ gemm_status grouped_autotune(const gemm_problem *problems, int count, int path, 
   // validate the problems once through the public entry point's checks
   gemm_status st = grouped_gemm(problems, count, path, nullptr, workspace, ws_bytes, stream);
   if (st) return st;
-  // candidate policies: all 128x128, all 64x64, padded-work rule at several costs
-  const double costs[] = {1.0, 1.3, 1.6, 2.0, 2.6};
-  struct Cand { int policy; double cost; };
-  std::vector<Cand> cands = {{0, 0.0}, {1, 0.0}};
-  for (double c : costs) cands.push_back({2, c});
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  // Candidate policies, all expressed as the padded-work rule's relative cost
+  // of a 64 x 64 tile element: 0 makes every tile 64 x 64, kNeverSmall every
+  // tile 128 x 128, the others weigh padding against the small tile's extra
+  // operand traffic.  The winner becomes the library's rule, so later
+  // grouped_default_variant choices reproduce the returned variants.
+  constexpr double kNeverSmall = 1e30;
+  const double costs[] = {kNeverSmall, 0.0, 1.0, 1.3, 1.6, 2.0, 2.6};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return hip_fail("grouped_autotune: event", he);
+  }
   float best_ms = 0.0f;
-  int best_i = -1;
+  double best_cost = kDefaultSmallCost;
+  bool have_best = false;
   std::vector<int> var(count), best_var(count);
-  for (size_t i = 0; i < cands.size(); ++i) {
-    for (int p = 0; p < count; ++p)
-      var[p] = cands[i].policy == 2 ? grouped_pick_variant(problems[p].M, problems[p].N, cands[i].cost)
-                                    : cands[i].policy;
+  for (double cost : costs) {
+    for (int p = 0; p < count; ++p) var[p] = grouped_pick_variant(problems[p].M, problems[p].N, cost);
     std::vector<Desc> descs;
     std::vector<int> starts;
     int total = 0;
@@ -156,20 +170,31 @@ gemm_status grouped_autotune(const gemm_problem *problems, int count, int path, 
     if ((st = grouped_upload(workspace, descs, starts, stream))) break;
     const int grid = grouped_grid(total);
     if ((st = grouped_enqueue(workspace, count, total, grid, stream))) break;  // warm-up
-    hipEventRecord(e0, stream);
-    for (int r = 0; r < reps; ++r) grouped_enqueue(workspace, count, total, grid, stream);
-    hipEventRecord(e1, stream);
-    hipEventSynchronize(e1);
+    he = hipEventRecord(e0, stream);
+    for (int r = 0; !st && he == hipSuccess && r < reps; ++r)
+      st = grouped_enqueue(workspace, count, total, grid, stream);
+    if (!st && he == hipSuccess) he = hipEventRecord(e1, stream);
+    if (!st && he == hipSuccess) he = hipEventSynchronize(e1);
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (best_i < 0 || ms < best_ms) { best_i = (int)i; best_ms = ms; best_var = var; }
+    if (!st && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (st) break;
+    if (he != hipSuccess) {
+      st = hip_fail("grouped_autotune: timing", he);
+      break;
+    }
+    if (!have_best || ms < best_ms) {
+      have_best = true;
+      best_ms = ms;
+      best_cost = cost;
+      best_var = var;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st) return st;
-  if (cands[best_i].policy == 2) {
+  {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_small_cost = cands[best_i].cost;
+    g_small_cost = best_cost;
   }
   std::memcpy(variants_out, best_var.data(), sizeof(int) * (size_t)count);
   return GEMM_STATUS_OK;

@@ -59,3 +59,50 @@ def check_split_result(oracle, A, B, C0, C, alpha, beta, n):
     if M * N * K >= REL_FRO_MIN_WORK:
         assert rel <= 1e-5, rel
     return rel
+
+
+# ---- FP8 matrix-core bound ---------------------------------------------------
+#
+# Accumulation into binary32: a componentwise error of up to 2.4 gamma_K
+# against the dequantised oracle was measured; the bound allows 8.
+FP8_MARGIN = 8
+# Within each group of eight consecutive k the f8f6f4 matrix core sums the
+# group's products and truncates the sum toward zero on a grid of 2^-11 of the
+# binade of the group's largest product (pinned by
+# test_gpu_fp8.py::test_group_sum_truncates_once_per_eight_k): one grid step
+# per group, at most 2^-11 of the group's largest |product|.
+FP8_GROUP_TRUNC = 2.0 ** -11
+FP8_GROUP = 8
+
+
+def fp8_group_term(qa, qb, sa, sb, alpha):
+    """Upper bound of the group truncation error of C[i,j]:
+    2^-11 |alpha| sa[i] sb[j] sum_g max_{k in g} |qa[i,k]| * max_{k in g} |qb[k,j]|
+    (the product of the group maxima bounds the group's largest product).
+    qa: M x K codes, qb: K x N codes, groups of eight k from k = 0."""
+    import oracle
+    M, K = qa.shape
+    N = qb.shape[1]
+    G = (K + FP8_GROUP - 1) // FP8_GROUP
+    a = np.zeros((M, G * FP8_GROUP))
+    a[:, :K] = np.abs(oracle.e4m3_decode(qa).astype(np.float64))
+    b = np.zeros((G * FP8_GROUP, N))
+    b[:K] = np.abs(oracle.e4m3_decode(qb).astype(np.float64))
+    amax = a.reshape(M, G, FP8_GROUP).max(axis=2)
+    bmax = b.reshape(G, FP8_GROUP, N).max(axis=1)
+    s = np.abs(alpha) * sa.astype(np.float64)[:, None] * sb.astype(np.float64)[None, :]
+    return FP8_GROUP_TRUNC * s * (amax @ bmax)
+
+
+def fp8_check(oracle, C, qa, qb, sa, sb, alpha, beta, C0):
+    """C of a scaled FP8 product (qa: M x K codes, qb: K x N codes) against the
+    dequantised-input oracle: |C - ref| <= 8 gamma_{K+4} |ref terms| + the
+    group truncation term, elementwise.  Returns (rel_fro, max ratio to the
+    bound, max ratio to |alpha||A||B| + |beta||C0| of the codes)."""
+    K = qa.shape[1]
+    ref = oracle.gemm_fp8_dequant(qa, sa, qb, sb, alpha=alpha, beta=beta, C0=C0)
+    den = oracle.gemm_fp8_dequant(qa & 0x7F, sa, qb & 0x7F, sb, alpha=abs(alpha),
+                                  beta=abs(beta), C0=None if C0 is None else np.abs(C0))
+    bound = FP8_MARGIN * gamma(K, extra=4) * den + fp8_group_term(qa, qb, sa, sb, alpha)
+    rel, _, _, ratio = oracle.norms(C, ref, bound)
+    return rel, ratio, oracle.norms(C, ref, den)[3]

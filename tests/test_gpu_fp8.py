@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import seeded_inputs as si
-from gpu_util import gamma, sample_rows
+from gpu_util import fp8_check, gamma, sample_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -137,30 +137,6 @@ def test_quantiser_reused_workspace(M, N, K):
         assert np.array_equal(qbT[:, :K].T, oracle.fp8_quantize_cols(B, rsb))
 
 
-# The matrix core's internal summation of one 64-deep FP8 block is not
-# specified to IEEE sequential-rounding accuracy; componentwise errors of up to
-# 2.4 gamma_K against the dequantised oracle were measured, so the pin allows 8.
-FP8_MARGIN = 8
-# Measured on gfx950 with hand-built codes: within a group of eight
-# consecutive k the f8f6f4 MFMA sums its products truncating toward zero at
-# about 2^-11 of the group's largest product (448*448 + 1*1 gives 448*448;
-# 448 + 7 * 2^-6 gives 448.0 + 0).  Rows dominated by one outlier column
-# therefore carry up to ~2^-11 |A||B| beyond the binary32 accumulation error;
-# the pin allows 2^-10.
-FP8_GROUP_TRUNC = 2.0 ** -10
-
-
-def fp8_bound(K):
-    return FP8_MARGIN * gamma(K, extra=4) + FP8_GROUP_TRUNC
-
-
-def _dequant_bound(qa, sa, qbT, sb, K, alpha, beta, C0):
-    qa_abs = qa[:, :K] & 0x7F
-    qb_abs = np.ascontiguousarray(qbT[:, :K].T) & 0x7F
-    return oracle.gemm_fp8_dequant(qa_abs, sa, qb_abs, sb, alpha=abs(alpha), beta=abs(beta),
-                                   C0=None if C0 is None else np.abs(C0))
-
-
 @pytest.mark.parametrize("M,N,K", [(256, 256, 256), (300, 520, 130), (1, 77, 300), (130, 1, 64),
                                    (513, 257, 1000), (64, 64, 1)])
 @pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (1.5, 0.5)])
@@ -174,11 +150,10 @@ def test_product_matches_dequantised_oracle(M, N, K, alpha, beta):
     torch.cuda.synchronize()
     C = dC.cpu().numpy()
     qb = np.ascontiguousarray(qbT[:, :K].T)
-    ref = oracle.gemm_fp8_dequant(qa[:, :K], sa, qb, sb, alpha=alpha, beta=beta, C0=C0)
-    den = _dequant_bound(qa, sa, qbT, sb, K, alpha, beta, C0)
-    cw = oracle.norms(C, ref, den)[3]
-    print("fp8 %dx%dx%d componentwise vs dequantised oracle: %.2f gamma_K" % (M, N, K, cw / gamma(K, extra=4)))
-    assert cw <= fp8_bound(K), cw
+    rel, ratio, cw = fp8_check(oracle, C, qa[:, :K], qb, sa, sb, alpha, beta, C0)
+    print("fp8 %dx%dx%d vs dequantised oracle: rel_fro %.2e, componentwise %.2f gamma_K, "
+          "%.3f of the bound" % (M, N, K, rel, cw / gamma(K, extra=4), ratio))
+    assert ratio <= 1.0, ratio
 
 
 @pytest.mark.parametrize("outliers", ["none", "A", "B"])
@@ -225,10 +200,7 @@ def test_full_size_sampled_rows():
     sa = h[L["sa"]:L["sa"] + 4 * M].view(np.float32)[rows]
     sb = h[L["sb"]:L["sb"] + 4 * N].view(np.float32)
     C = dC.cpu().numpy()[rows]
-    ref = oracle.gemm_fp8_dequant(qa, sa, qb, sb, alpha=1.5, beta=0.5, C0=C0[rows])
-    den = oracle.gemm_fp8_dequant(qa & 0x7F, sa, qb & 0x7F, sb, alpha=1.5, beta=0.5,
-                                  C0=np.abs(C0[rows]))
-    assert oracle.norms(C, ref, den)[3] <= fp8_bound(K)
+    assert fp8_check(oracle, C, qa, qb, sa, sb, 1.5, 0.5, C0[rows])[1] <= 1.0
     exact = oracle.gemm(A[rows], B, alpha=1.5, beta=0.5, C0=C0[rows])
     assert oracle.rel_fro(C, exact) <= 0.08
 
@@ -256,10 +228,8 @@ def test_every_config_matches_dequantised_oracle(M, N, K):
         sa = h[L["sa"]:L["sa"] + 4 * M].view(np.float32)
         sb = h[L["sb"]:L["sb"] + 4 * N].view(np.float32)
         qb = np.ascontiguousarray(qbT[:, :K].T)
-        ref = oracle.gemm_fp8_dequant(qa[:, :K], sa, qb, sb, alpha=1.5, beta=0.5, C0=C0)
-        den = _dequant_bound(qa, sa, qbT, sb, K, 1.5, 0.5, C0)
-        cw = oracle.norms(dC.cpu().numpy(), ref, den)[3]
-        assert cw <= fp8_bound(K), (mm.gemm_config_name(mm.PATH_FP8, cfg), cw)
+        ratio = fp8_check(oracle, dC.cpu().numpy(), qa[:, :K], qb, sa, sb, 1.5, 0.5, C0)[1]
+        assert ratio <= 1.0, (mm.gemm_config_name(mm.PATH_FP8, cfg), ratio)
 
 
 def _workspace_from_codes(mm, qa, qb, sa, sb):
@@ -302,3 +272,39 @@ def test_integer_codes_are_exact(M, N, K):
                            dC, N, workspace=ws, ws_bytes=nbytes)
         torch.cuda.synchronize()
         assert np.array_equal(dC.cpu().numpy().astype(np.int64), IA @ IB), cfg
+
+
+def test_group_sum_truncates_once_per_eight_k():
+    """Pins the model behind the FP8 bound with hand-built codes (unit
+    scales, M = N = 1, K = 64).  Products 448 (k = 0) and seven of 2^-4
+    (k = 1..7): the exact sum 448.4375 lies between grid points 448.375 and
+    448.5 of 2^-11 of the binade of 448 (step 2^-3).  A group sum truncated
+    once gives 448.375; truncating each product before summing would give
+    448.0.  With the seven small products at k = 8..14 instead (the next
+    group of eight) both groups are exact and the binary32 sum is 448.4375."""
+    import torch
+    import paper_1902_10345_amd as mm
+    K = 64
+    one, small, big = (oracle.e4m3_encode(np.array([v], np.float32))[0]
+                       for v in (1.0, 2.0 ** -4, 448.0))
+    results = {}
+    for case, ks in (("same_group", range(1, 8)), ("next_group", range(8, 15))):
+        qa = np.zeros((1, K), np.uint8)
+        qb = np.zeros((K, 1), np.uint8)
+        qa[0, 0] = big
+        qb[0, 0] = one
+        for k in ks:
+            qa[0, k] = small
+            qb[k, 0] = one
+        ws, nbytes = _workspace_from_codes(mm, qa, qb, np.ones(1), np.ones(1))
+        got = []
+        for cfg in range(mm.gemm_num_configs(mm.PATH_FP8)):
+            dC = torch.full((1, 1), float("nan"), device="cuda")
+            mm.gemm_run_config(mm.PATH_FP8_PREQUANTIZED, cfg, 1, 1, K, 1.0, None, 0, None, 0,
+                               0.0, dC, 1, workspace=ws, ws_bytes=nbytes)
+            torch.cuda.synchronize()
+            got.append(float(dC.cpu()[0, 0]))
+        results[case] = got
+    print("fp8 group sums:", results)
+    assert all(v == 448.375 for v in results["same_group"]), results
+    assert all(v == 448.4375 for v in results["next_group"]), results

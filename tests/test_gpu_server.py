@@ -76,6 +76,10 @@ def test_alone_and_in_the_mix_are_bitwise_equal_and_correct():
         _wait(mm, srv, tickets)
         st = mm.server_stats(srv)
         assert st["completed"] == len(reqs)
+        # the requests really were in a mix: several admitted at once, and
+        # steps on different streams in flight together
+        assert st["max_in_flight"] > 1, st
+        assert st["max_concurrent_steps"] > 1, st
     finally:
         mm.server_destroy(srv)
     for (M, N, K, A, B, C0), (hA, hB, hC0, hC) in zip(reqs, bufs):
@@ -172,5 +176,143 @@ def test_drain_and_stats():
         st = mm.server_stats(srv)
         assert st["completed"] == 20 and st["p99_ms"] >= st["p50_ms"] > 0
         assert all(np.all(o.numpy() == 256.0) for o in outs)
+    finally:
+        mm.server_destroy(srv)
+
+
+def test_injected_step_failure_is_reported_per_request():
+    """A step that cannot be enqueued (forced from the host) ends its requests
+    with GEMM_STATUS_HIP_ERROR -- never with OK and an unwritten result --
+    gives their slots and arena ranges back, and later requests run."""
+    import os
+    import torch
+    import paper_1902_10345_amd as mm
+    os.environ["GEMM_SERVER_INJECT_STEP_FAILURES"] = "1"
+    try:
+        arena, srv = _server(mm, 1 << 26, slots=8, streams=2)
+    finally:
+        del os.environ["GEMM_SERVER_INJECT_STEP_FAILURES"]
+    try:
+        A = torch.ones((64, 64), pin_memory=True)
+        hC = torch.full((64, 64), -1.0, pin_memory=True)
+        t = mm.server_submit(srv, 64, 64, 64, 1.0, A, A, 0.0, None, hC)
+        t0 = time.time()
+        status = None
+        while time.time() - t0 < 30:
+            try:
+                if mm.server_poll(srv, t) is not None:
+                    status = mm.STATUS_OK
+                    break
+            except mm.GemmError as e:
+                status = e.status
+                break
+            time.sleep(0.001)
+        assert status == mm.STATUS_HIP_ERROR
+        assert np.all(hC.numpy() == -1.0)           # nothing was written
+        st = mm.server_stats(srv)
+        assert st["failed"] == 1 and st["completed"] == 0
+        # the ticket is forgotten after it was reported
+        with pytest.raises(mm.GemmError) as e:
+            mm.server_poll(srv, t)
+        assert e.value.status == mm.STATUS_UNKNOWN
+        # the server keeps serving
+        hC2 = torch.empty((64, 64), pin_memory=True)
+        t2 = mm.server_submit(srv, 64, 64, 64, 1.0, A, A, 0.0, None, hC2)
+        _wait(mm, srv, [t2])
+        assert np.all(hC2.numpy() == 64.0)
+        mm.server_drain(srv, 30.0)
+    finally:
+        mm.server_destroy(srv)
+
+
+def _poll_status(mm, srv, t, timeout=30.0):
+    t0 = time.time()
+    while time.time() - t0 < timeout:
+        try:
+            if mm.server_poll(srv, t) is not None:
+                return mm.STATUS_OK
+        except mm.GemmError as e:
+            return e.status
+        time.sleep(0.001)
+    raise AssertionError("request did not end")
+
+
+def test_queue_timeout_drops_stale_requests():
+    """A request whose arrival stamp is older than the queue timeout is
+    dropped before admission (the timeout check precedes admission in every
+    scheduler pass) and reported as GEMM_STATUS_TIMED_OUT; fresh requests
+    are served."""
+    import torch
+    import paper_1902_10345_amd as mm
+    arena, srv = _server(mm, 1 << 26, slots=4, streams=2)
+    try:
+        mm.server_set_queue_timeout(srv, 1.0)
+        A = torch.ones((32, 32), pin_memory=True)
+        hC = torch.full((32, 32), -1.0, pin_memory=True)
+        hC2 = torch.empty((32, 32), pin_memory=True)
+        time.sleep(0.05)
+        stale = mm.server_submit(srv, 32, 32, 32, 1.0, A, A, 0.0, None, hC,
+                                 mm.server_now(srv) - 10.0)
+        fresh = mm.server_submit(srv, 32, 32, 32, 1.0, A, A, 0.0, None, hC2)
+        assert _poll_status(mm, srv, stale) == mm.STATUS_TIMED_OUT
+        assert _poll_status(mm, srv, fresh) == mm.STATUS_OK
+        assert np.all(hC.numpy() == -1.0) and np.all(hC2.numpy() == 32.0)
+        with pytest.raises(mm.GemmError):
+            mm.server_set_queue_timeout(srv, -1.0)
+    finally:
+        mm.server_destroy(srv)
+
+
+def test_cancel_a_queued_request():
+    """With one slot, a request submitted right behind a large one waits in
+    the queue; cancelling it reports GEMM_STATUS_CANCELLED and its result
+    buffer is never written.  (Should the large request finish before the
+    cancel lands, the second one is admitted and the cancel is refused with
+    NOT_READY; the pair is then tried again.)"""
+    import torch
+    import paper_1902_10345_amd as mm
+    arena, srv = _server(mm, 1 << 28, slots=1, streams=2)
+    try:
+        n = 1536
+        big = torch.rand((n, n), pin_memory=True)
+        hbig = torch.empty((n, n), pin_memory=True)
+        A = torch.ones((16, 16), pin_memory=True)
+        cancelled = False
+        for _ in range(3):
+            hC = torch.full((16, 16), -1.0, pin_memory=True)
+            t1 = mm.server_submit(srv, n, n, n, 1.0, big, big, 0.0, None, hbig)
+            t2 = mm.server_submit(srv, 16, 16, 16, 1.0, A, A, 0.0, None, hC)
+            try:
+                mm.server_cancel(srv, t2)
+                cancelled = True
+            except mm.GemmError as err:
+                assert err.status == mm.STATUS_NOT_READY
+            _wait(mm, srv, [t1])
+            if cancelled:
+                assert _poll_status(mm, srv, t2) == mm.STATUS_CANCELLED
+                assert np.all(hC.numpy() == -1.0)
+                break
+            assert _poll_status(mm, srv, t2) == mm.STATUS_OK
+        assert cancelled
+        with pytest.raises(mm.GemmError) as e:
+            mm.server_cancel(srv, 123456789)
+        assert e.value.status == mm.STATUS_UNKNOWN
+        mm.server_drain(srv, 30.0)
+    finally:
+        mm.server_destroy(srv)
+
+
+def test_offsets_beyond_32_bits_are_refused_at_submit():
+    """K (or N) so large that the grouped tile body's 32-bit offsets would
+    wrap is refused with GEMM_STATUS_UNSUPPORTED before anything is copied,
+    even when the operands would fit the arena, and counts as rejected."""
+    import paper_1902_10345_amd as mm
+    arena, srv = _server(mm, 1 << 26, slots=4, streams=1)
+    try:
+        for (M, N, K) in [(1, 1, 5_000_000), (1, 20_000_000, 1)]:
+            with pytest.raises(mm.GemmError) as e:
+                mm.server_submit(srv, M, N, K, 1.0, 16, 16, 0.0, None, 16)
+            assert e.value.status == mm.STATUS_UNSUPPORTED
+        assert mm.server_stats(srv)["rejected"] == 2
     finally:
         mm.server_destroy(srv)

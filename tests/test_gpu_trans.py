@@ -187,18 +187,15 @@ def test_fp8_column_major_against_dequantised_oracle(ta, tb, outliers):
     """Column-major FP8 runs the row-major product C^T = op(B)^T op(A)^T:
     op(A)'s rows and op(B)'s columns keep their scales, so the result obeys
     the same dequantised-input bound as the row-major path."""
-    from test_gpu_fp8 import fp8_bound
+    from gpu_util import fp8_check
     import paper_1902_10345_amd as mm
     M, N, K = 260, 300, 1000
     A, B, C0 = si.fp8_workload(M, N, K, 71, outliers=outliers)
     C = Problem(A, B, C0, "F", ta, tb).run(mm, 1.5, 0.5, mm.PATH_FP8)
     sa, sb = oracle.fp8_scales_rows(A), oracle.fp8_scales_cols(B)
     qa, qb = oracle.fp8_quantize_rows(A, sa), oracle.fp8_quantize_cols(B, sb)
-    ref = oracle.gemm_fp8_dequant(qa, sa, qb, sb, alpha=1.5, beta=0.5, C0=C0)
-    den = oracle.gemm_fp8_dequant(qa & 0x7F, sa, qb & 0x7F, sb, alpha=1.5, beta=0.5,
-                                  C0=np.abs(C0))
-    cw = oracle.norms(C, ref, den)[3]
-    assert cw <= fp8_bound(K), (cw, fp8_bound(K))
+    ratio = fp8_check(oracle, C, qa, qb, sa, sb, 1.5, 0.5, C0)[1]
+    assert ratio <= 1.0, ratio
 
 
 # Shapes on which the library picks the larger tiles: 256 x 128 x 32 and

@@ -341,6 +341,94 @@ def test_fp8_quantize_uses_scale_division():
     assert list(oracle.e4m3_decode(q)[0]) == [448.0, 224.0, 1.0, -3.0]
 
 
+def _read_fp8_scaled_golden():
+    rows = {}
+    with open(os.path.join(GOLDEN, "fp8_scaled.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            key, *vals = line.split()
+            conv = (lambda v: int(v, 16)) if key in ("qrow", "qcol", "dq_qa", "dq_qb") else float
+            rows.setdefault(key, []).append([conv(v) for v in vals])
+    return rows
+
+
+def test_fp8_scaled_quantisation_hand_fixture():
+    """Hand-derived scales and codes for a 3 x 4 matrix quantised by rows and
+    by columns with distinct, non-unit scales (tests/golden/fp8_scaled.txt):
+    a scale taken from the wrong row or column, or a missing division, changes
+    at least one code."""
+    g = _read_fp8_scaled_golden()
+    X = np.array(g["X"], dtype=np.float32)
+    srow = oracle.fp8_scales_rows(X)
+    scol = oracle.fp8_scales_cols(X)
+    assert np.array_equal(srow, np.array(g["srow"][0], dtype=np.float32))
+    assert np.array_equal(scol, np.array(g["scol"][0], dtype=np.float32))
+    assert np.array_equal(oracle.fp8_quantize_rows(X, srow), np.array(g["qrow"], dtype=np.uint8))
+    assert np.array_equal(oracle.fp8_quantize_cols(X, scol), np.array(g["qcol"], dtype=np.uint8))
+
+
+def test_fp8_dequant_hand_fixture():
+    """A 2 x 2 x 2 dequantised product with distinct row and column scales,
+    computed by hand (tests/golden/fp8_scaled.txt); exchanging the roles of
+    sa and sb, or applying one of them twice, changes the off-diagonal
+    entries."""
+    g = _read_fp8_scaled_golden()
+    qa = np.array(g["dq_qa"], dtype=np.uint8)
+    qb = np.array(g["dq_qb"], dtype=np.uint8)
+    sa = np.array(g["dq_sa"][0], dtype=np.float32)
+    sb = np.array(g["dq_sb"][0], dtype=np.float32)
+    got = oracle.gemm_fp8_dequant(qa, sa, qb, sb)
+    assert np.array_equal(got, np.array(g["dq_C"], dtype=np.float64))
+
+
+def _e4m3_grid_matrix(g, rows, cols, exps, axis):
+    """Random values on the E4M3 grid, multiplied by 2^exps along `axis`
+    (exps[i] for row i when axis == 1, exps[j] for column j when axis == 0),
+    with one entry of each row (column) equal to +-448 * 2^exps so that its
+    maximum is exactly that."""
+    vals = np.array([oracle.e4m3_value(c) for c in range(127)], dtype=np.float64)
+    x = vals[g.integers(0, 127, size=(rows, cols))] * g.choice([-1.0, 1.0], size=(rows, cols))
+    if axis == 1:
+        x[np.arange(rows), g.integers(0, cols, size=rows)] = 448.0 * g.choice([-1.0, 1.0], size=rows)
+        x *= np.exp2(np.asarray(exps, dtype=np.float64))[:, None]
+    else:
+        x[g.integers(0, rows, size=cols), np.arange(cols)] = 448.0 * g.choice([-1.0, 1.0], size=cols)
+        x *= np.exp2(np.asarray(exps, dtype=np.float64))[None, :]
+    return x.astype(np.float32)
+
+
+def test_fp8_scaled_product_equals_gemm_with_power_of_two_scales():
+    """Rows of A and columns of B on the E4M3 grid times distinct powers of
+    two 2^e_i, 2^f_j, each with maximum 448 * 2^e_i (448 * 2^f_j), and
+    M != N: the scales must be exactly 2^e_i and 2^f_j, quantisation must
+    then be exact, and the dequantised product -- sa[i] * sb[j] times the sum
+    of code products -- must equal the plain product bit for bit (a power of
+    two applied to every term of a sum does not change its rounding).  A scale
+    indexed by the wrong row or column, a missing or doubled scale, or a
+    quantiser dividing by the wrong scale fails one of the assertions."""
+    g = np.random.default_rng(29)
+    M, N, K = 6, 9, 40
+    e = g.permutation(np.arange(-12, 13))[:M]
+    f = g.permutation(np.arange(-12, 13))[:N]
+    A = _e4m3_grid_matrix(g, M, K, e, axis=1)
+    B = _e4m3_grid_matrix(g, K, N, f, axis=0)
+    sa, sb = oracle.fp8_scales_rows(A), oracle.fp8_scales_cols(B)
+    assert np.array_equal(sa, np.exp2(e).astype(np.float32))
+    assert np.array_equal(sb, np.exp2(f).astype(np.float32))
+    qa, qb = oracle.fp8_quantize_rows(A, sa), oracle.fp8_quantize_cols(B, sb)
+    assert np.array_equal(oracle.e4m3_decode(qa).astype(np.float64) * np.exp2(e)[:, None], A)
+    assert np.array_equal(oracle.e4m3_decode(qb).astype(np.float64) * np.exp2(f)[None, :], B)
+    C0 = si.uniform((M, N), 30)
+    for alpha, beta in ((1.0, 0.0), (1.5, 0.5), (-0.75, 2.0)):
+        d = oracle.gemm_fp8_dequant(qa, sa, qb, sb, alpha=alpha, beta=beta, C0=C0)
+        assert np.array_equal(d, oracle.gemm(A, B, alpha=alpha, beta=beta, C0=C0))
+    # sensitivity: the same codes with the scale vectors reversed differ
+    d_rev = oracle.gemm_fp8_dequant(qa, sa[::-1].copy(), qb, sb[::-1].copy())
+    assert not np.array_equal(d_rev, oracle.gemm(A, B))
+
+
 # ---------------------------------------------------------------- norms ---
 
 def test_norms_match_numpy():
