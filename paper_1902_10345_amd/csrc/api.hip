@@ -90,6 +90,20 @@ static int pick_config(int path, int n_products, int64_t M, int64_t N, int64_t K
   }
 }
 
+gemm_status check_f32_args(const char *fn, int64_t M, int64_t N, int64_t K, float alpha,
+                           const float *A, int64_t lda, const float *B, int64_t ldb,
+                           const float *C, int64_t ldc, bool &noop, bool &scale_only) {
+  Checked ck;
+  const gemm_status st = check_gemm_args(fn, M, N, K, alpha, A, lda, B, ldb, C, ldc, ck);
+  noop = ck.noop;
+  scale_only = ck.scale_only;
+  return st;
+}
+
+int library_config(int path, int n_products, int64_t M, int64_t N, int64_t K) {
+  return pick_config(path, n_products, M, N, K);
+}
+
 }  // namespace mm
 
 using namespace mm;
@@ -380,9 +394,10 @@ gemm_status gemm_ex(int order, int trans_a, int trans_b, int64_t M, int64_t N, i
   }
   const bool trans = g.ta || g.tb;
   if (path == GEMM_PATH_F32) {
-    // transposed operands run on the FP32 matrix-core tiles only
+    // transposed operands run on the FP32 matrix-core and small-product
+    // tiles only
     int cfg = pick_config(GEMM_PATH_F32, 0, g.M, g.N, K);
-    if (trans && cfg != 5 && cfg != 6) {
+    if (trans && (cfg < 5 || cfg > 8)) {
       const int64_t big = ((g.M + 255) / 256) * ((g.N + 255) / 256);
       cfg = big >= num_cus() ? 5 : 6;
     }

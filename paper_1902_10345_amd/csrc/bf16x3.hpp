@@ -57,6 +57,16 @@ __device__ __forceinline__ void split3(f32x2 x, bf16x2 &h, bf16x2 &m, bf16x2 &l)
   l = __builtin_convertvector(r - __builtin_convertvector(m, f32x2), bf16x2);
 }
 
+// f(std::integral_constant<int, i>{}) for i = 0 .. N-1, unrolled at compile
+// time (every index is a constant expression inside f).
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
+  }
+}
+
 // XOR swizzle of the 16-byte chunk index of an LDS row holding BK bf16.
 template <int BK>
 __device__ __forceinline__ int swz(int r) {
@@ -153,6 +163,37 @@ struct Stage {
         voff[i] = n < nrows ? n * 4 : (int)0x80000000;
         soff[i] = __builtin_amdgcn_readfirstlane(8 * chunk_of(idx)) * ld4;
       }
+    }
+  }
+
+  // Item i of a full slab (every k of the slab in [0, K)), on its own: the
+  // pieces a software-pipelined loop places between its MFMAs.
+  template <int SET>
+  __device__ __forceinline__ void load_item(int i, int k0) {
+    if constexpr (KC) {
+      const int off = voff[i] + k0 * 4;
+      if constexpr (V) {
+        const float4 v0 =
+            __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+        const float4 v1 =
+            __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, 0));
+        r[SET][i][0] = v0.x; r[SET][i][1] = v0.y; r[SET][i][2] = v0.z; r[SET][i][3] = v0.w;
+        r[SET][i][4] = v1.x; r[SET][i][5] = v1.y; r[SET][i][6] = v1.z; r[SET][i][7] = v1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          r[SET][i][e] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off + 4 * e, 0, 0));
+      }
+    } else {
+      const int ld4 = (int)ld * 4;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(P + (int64_t)(k0 > 0 ? k0 : 0) * ld + r0), (short)0,
+          k0 >= 0 ? (int)(((int64_t)(BK - 1) * ld + nrows) * 4) : 0, kBufferFlags);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        r[SET][i][e] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff[i], soff[i] + e * ld4, 0));
     }
   }
 
@@ -445,6 +486,8 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   // the loads it needs.
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
+  // one wave per SIMD with 128 x 128 wave tiles: the deeply pipelined loop
+  constexpr bool kDeep = NP >= 2 && NW == 4 && WM == 128 && WN == 128 && BK == 16;
   using Fast = std::true_type;
   using Masked = std::false_type;
   const int KT = (K + BK - 1) / BK;
@@ -471,6 +514,116 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       sstore(S0{}, 0);
       __syncthreads();
     }
+  } else if constexpr (kDeep) {
+    // One wave per SIMD (4 waves of 128 x 128): no other wave hides a stall,
+    // so every latency is covered inside the wave.  Slab s is loaded from
+    // global memory in step s-3 (register set s%2), split and written to LDS
+    // stage s%2 in step s-2, read into fragment set s%2 in step s-1 and
+    // multiplied in step s.  The MFMAs of a step depend on nothing issued in
+    // that step; the barrier at its end orders the writes of slab s+2 before
+    // their reads (next step) and the reads of slab s+1 before stage (s+1)%2
+    // is overwritten (next step).  The other work of a step is placed between
+    // its MFMAs in a fixed order (scheduling barriers keep the compiler from
+    // regrouping it): the global loads first, then the fragment reads, then
+    // the split and LDS writes one item at a time.
+    constexpr int kProd = NP == 2 ? 3 : 6;
+    constexpr int kBlk = G::FM * G::FN;
+    constexpr int kMfma = kBlk * kProd;
+    constexpr int kReads = (G::FM + G::FN) * NP;
+    constexpr int kItems = SA::ITEMS + SB::ITEMS;
+    constexpr int kRead0 = kItems;                 // first MFMA slot with fragment reads
+    constexpr int kSplit0 = kRead0 + (kReads + 1) / 2;  // first slot of the split
+    static_assert(kSplit0 + 4 * kItems <= kMfma, "the step's work fits between its MFMAs");
+    // product q of the step: planes (pa, pb), small products first
+    auto mfma_one = [&](const Frags &f, auto Q) {
+      constexpr int q = decltype(Q)::value;
+      constexpr int pr = q / kBlk, bi = (q % kBlk) / G::FN, bj = q % G::FN;
+      constexpr int pa = NP == 2 ? (pr == 0 ? 1 : 0) : (pr < 3 ? 2 - pr : (pr == 3 ? 1 : 0));
+      constexpr int pb = NP == 2 ? (pr == 1 ? 1 : 0) : (pr < 3 ? pr : (pr == 4 ? 1 : 0));
+      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[pa][bi], f.b[pb][bj], acc[bi][bj],
+                                                            0, 0, 0);
+    };
+    // fragment read r of a slab: B planes then A planes, one 32-row block each
+    auto read_one = [&](Frags &f, int stage, auto R) {
+      constexpr int r = decltype(R)::value;
+      const __bf16 *sA = lds + stage * G::STAGE;
+      const __bf16 *sB = sA + G::NPL * G::PLANE_A;
+      const int c = lgrp;  // one k-step per slab: logical chunk 0 or 1
+      if constexpr (r < NP * G::FN) {
+        constexpr int p = r / G::FN, j = r % G::FN;
+        const int n = wn0 + j * 32 + lrow;
+        f.b[p][j] = *reinterpret_cast<const bf16x8 *>(sB + p * G::PLANE_B + n * BK +
+                                                      ((c ^ swz<BK>(n)) << 3));
+      } else {
+        constexpr int p = (r - NP * G::FN) / G::FM, i = (r - NP * G::FN) % G::FM;
+        const int rr = wm0 + i * 32 + lrow;
+        f.a[p][i] = *reinterpret_cast<const bf16x8 *>(sA + p * G::PLANE_A + rr * BK +
+                                                      ((c ^ swz<BK>(rr)) << 3));
+      }
+    };
+    // the split of item it (A items first, then B items), one value pair at a
+    // time, and its LDS writes with the last pair
+    bf16x8 sp[NP];
+    auto split_pair = [&](auto S, int stage, auto IT, auto E) {
+      constexpr int set = decltype(S)::value;
+      constexpr int it = decltype(IT)::value, e = 2 * decltype(E)::value;
+      const float *x;
+      if constexpr (it < SA::ITEMS) x = sa.r[set][it];
+      else x = sb.r[set][it - SA::ITEMS];
+      bf16x2 x0, x1, x2;
+      if constexpr (NP == 2) split2(f32x2{x[e], x[e + 1]}, x0, x1);
+      else split3(f32x2{x[e], x[e + 1]}, x0, x1, x2);
+      sp[0][e] = x0.x; sp[0][e + 1] = x0.y;
+      sp[1][e] = x1.x; sp[1][e + 1] = x1.y;
+      if constexpr (NP == 3) { sp[2][e] = x2.x; sp[2][e + 1] = x2.y; }
+      if constexpr (e == 6) {
+        __bf16 *sA = lds + stage * G::STAGE;
+        __bf16 *base = it < SA::ITEMS ? sA : sA + G::NPL * G::PLANE_A;
+        constexpr int PLANE = it < SA::ITEMS ? G::PLANE_A : G::PLANE_B;
+        const int idx = tid + NT * (it < SA::ITEMS ? it : it - SA::ITEMS);
+        const int rr = it < SA::ITEMS ? SA::row_of(idx) : SB::row_of(idx);
+        const int cc = it < SA::ITEMS ? SA::chunk_of(idx) : SB::chunk_of(idx);
+        const int off = rr * BK + ((cc ^ swz<BK>(rr)) << 3);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) *reinterpret_cast<bf16x8 *>(base + p * PLANE + off) = sp[p];
+      }
+    };
+    auto step = [&](auto LS, int kload, auto SS, int wstage, Frags &fn, int rstage,
+                    const Frags &fc) {
+      constexpr int lset = decltype(LS)::value;
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<kMfma>([&](auto Q) {
+        constexpr int m = decltype(Q)::value;
+        mfma_one(fc, Q);
+        if constexpr (m < SA::ITEMS) sa.template load_item<lset>(m, kload);
+        else if constexpr (m < kItems) sb.template load_item<lset>(m - SA::ITEMS, kload);
+        if constexpr (m >= kRead0 && 2 * (m - kRead0) < kReads) {
+          read_one(fn, rstage, std::integral_constant<int, 2 * (m - kRead0)>{});
+          if constexpr (2 * (m - kRead0) + 1 < kReads)
+            read_one(fn, rstage, std::integral_constant<int, 2 * (m - kRead0) + 1>{});
+        }
+        if constexpr (m >= kSplit0 && m < kSplit0 + 4 * kItems)
+          split_pair(SS, wstage, std::integral_constant<int, (m - kSplit0) / 4>{},
+                     std::integral_constant<int, (m - kSplit0) % 4>{});
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    };
+    Frags f0, f1;
+    if (KT > 1) gload(S1{}, Fast{}, kslab(1));
+    else gload(S1{}, Masked{}, kbase);
+    sstore(S1{}, 1);
+    if (KT > 1) gload(S0{}, Fast{}, kslab(2));
+    else gload(S0{}, Masked{}, kbase);
+    __syncthreads();
+    frag_read(f0, 0, 0);
+    __syncthreads();
+    for (; t + 2 <= KT; t += 2) {
+      step(S1{}, kslab(t + 3), S0{}, 0, f1, 1, f0);
+      __syncthreads();
+      step(S0{}, kslab(t + 4), S1{}, 1, f0, 0, f1);
+      __syncthreads();
+    }
+    if (t < KT) frag_mfma(f0);  // odd slab count: the last slab is in f0
   } else if constexpr (NP == 1) {
     // FP32 mode, two register sets: 64 MFMAs per wave and slab leave the
     // loads and stores plenty of room; the compiler schedules them.
@@ -531,8 +684,10 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       __syncthreads();
     }
   }
-  if (t < KT) {  // odd slab count: the last slab sits in stage 0
-    mfma_stage(0);
+  if constexpr (!kDeep) {
+    if (t < KT) {  // odd slab count: the last slab sits in stage 0
+      mfma_stage(0);
+    }
   }
 
   // ---- peeled epilogue ----------------------------------------------------

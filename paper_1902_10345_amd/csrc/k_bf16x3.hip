@@ -152,6 +152,13 @@ static const Bx3Config kBx3Configs[] = {
     {{64, 64, 32, "bx3_64x64x32_4w32x32_p3"}, 2},
     {{256, 256, 16, "bx3_256x256x16_4w128x128_p3"}, 2},
     {{128, 128, 16, "bx3_128x128x16_4w64x64_p3"}, 2},
+    // small products: one tile per workgroup of 8 waves, its k range split
+    // over the waves (fragments straight from global memory, ordered sum
+    // through LDS)
+    {{32, 32, 16, "bx3_small_32x32_8wk_p3"}, 2},
+    {{64, 64, 16, "bx3_small_64x64_8wk_p3"}, 2},
+    {{32, 32, 16, "bx3_small_32x32_8wk_p6"}, 3},
+    {{64, 64, 16, "bx3_small_64x64_8wk_p6"}, 3},
 };
 
 int bx3_num_configs() { return (int)(sizeof(kBx3Configs) / sizeof(kBx3Configs[0])); }
@@ -181,6 +188,7 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
 }
 
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
+  if (cfg >= 9 && cfg <= 12) return small_run(g, (cfg - 9) & 1, cfg <= 10 ? 2 : 3, s);
   if (g.ta || g.tb) return g.ta ? (g.tb ? bx3_run_tt(g, cfg, s) : bx3_run_tn(g, cfg, s)) : bx3_run_nt(g, cfg, s);
   switch (cfg) {
     case 0: return bx3::launch<256, 256, 16, 128, 64, 2, 8>(g, s);

@@ -256,6 +256,10 @@ static const TileConfig kF32Configs[] = {
     // body of the split-precision path in its FP32 mode)
     {256, 256, 16, "f32mfma_256x256x16_8w128x64"},
     {128, 128, 16, "f32mfma_128x128x16_4w64x64"},
+    // small products: one tile per workgroup of 8 waves, its k range split
+    // over the waves (binary32 matrix cores, ordered sum through LDS)
+    {32, 32, 8, "f32_small_32x32_8wk"},
+    {64, 64, 8, "f32_small_64x64_8wk"},
 };
 
 int f32_num_configs() { return (int)(sizeof(kF32Configs) / sizeof(kF32Configs[0])); }
@@ -273,8 +277,8 @@ int f32_default_config(int64_t M, int64_t N, int64_t K) {
 }
 
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
-  if ((g.ta || g.tb) && cfg != 5 && cfg != 6) {
-    set_error("gemm_ex: only the FP32 matrix-core tiles take transposed operands");
+  if ((g.ta || g.tb) && cfg != 5 && cfg != 6 && cfg != 7 && cfg != 8) {
+    set_error("gemm_ex: only the FP32 matrix-core and small-product tiles take transposed operands");
     return GEMM_STATUS_UNSUPPORTED;
   }
   switch (cfg) {
@@ -285,6 +289,8 @@ gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 4: return f32::launch<128, 64, 32, 8, 4, 2>(g, s);
     case 5: return f32mfma_run(g, 0, s);
     case 6: return f32mfma_run(g, 1, s);
+    case 7: return small_run(g, 0, 1, s);
+    case 8: return small_run(g, 1, 1, s);
     default: set_error("gemm_f32: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

@@ -50,6 +50,9 @@ int bx3_splitk_default(int64_t M, int64_t N, int64_t K);
 gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s);
 size_t bx3_splitk_ws_bytes(int64_t M, int64_t N, int splits);
 gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *ws, hipStream_t s);
+// Small products (k_small.hip): which 0 = 32 x 32 tiles, 1 = 64 x 64; np 1 =
+// binary32 matrix cores, 2 / 3 = bf16 planes per operand (3 / 6 products).
+gemm_status small_run(const GemmArgs &g, int which, int np, hipStream_t s);
 // Batched-strided products (binary32 or split precision) on the MFMA tiles.
 int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, int64_t batch);
 gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,
@@ -89,6 +92,15 @@ const char *fp8_config_name(int cfg);
 gemm_status fp8_gemm_run_cfg(int64_t M, int64_t N, int64_t K, float alpha, const void *ws,
                              float beta, float *C, int64_t ldc, int cfg, hipStream_t s);
 gemm_status fp8_encode_run(int64_t n, const float *x, uint8_t *out, hipStream_t s);
+
+// Argument rules of the (M,N,K,alpha,A,lda,B,ldb,beta,C,ldc) prefix shared by
+// the binary32 entry points (BLAS order, -index on a bad argument); noop:
+// M == 0 or N == 0; scale_only: alpha == 0 or K == 0 (C <- beta*C).
+gemm_status check_f32_args(const char *fn, int64_t M, int64_t N, int64_t K, float alpha,
+                           const float *A, int64_t lda, const float *B, int64_t ldb,
+                           const float *C, int64_t ldc, bool &noop, bool &scale_only);
+// The configuration an entry point of `path` runs (tuned, else the default).
+int library_config(int path, int n_products, int64_t M, int64_t N, int64_t K);
 
 // Autotuner table: the tuned configuration for this size bucket, or -1.
 int tuned_config(int path, int n_products, int64_t M, int64_t N, int64_t K);

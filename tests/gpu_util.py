@@ -66,18 +66,21 @@ def check_split_result(oracle, A, B, C0, C, alpha, beta, n):
 # Accumulation into binary32: a componentwise error of up to 2.4 gamma_K
 # against the dequantised oracle was measured; the bound allows 8.
 FP8_MARGIN = 8
-# Within each group of eight consecutive k the f8f6f4 matrix core sums the
-# group's products and truncates the sum toward zero on a grid of 2^-11 of the
-# binade of the group's largest product (pinned by
-# test_gpu_fp8.py::test_group_sum_truncates_once_per_eight_k): one grid step
-# per group, at most 2^-11 of the group's largest |product|.
-FP8_GROUP_TRUNC = 2.0 ** -11
+# Within each group of eight consecutive k the f8f6f4 matrix core truncates
+# every product toward zero to a multiple of 2^(E - 13), E the exponent of the
+# group's largest product, before summing the group (pinned on hand-built codes
+# by test_gpu_fp8.py::test_group_products_truncate_toward_zero_on_the_group_grid).
+# The largest product and any of its binade are on that grid, so at most seven
+# products lose less than one step each: less than 7 * 2^-13 of the group's
+# largest |product|, itself at most the product of the group's maxima (which
+# also covers an alignment on the maxima's exponents).
+FP8_GROUP_TRUNC = 7 * 2.0 ** -13
 FP8_GROUP = 8
 
 
 def fp8_group_term(qa, qb, sa, sb, alpha):
     """Upper bound of the group truncation error of C[i,j]:
-    2^-11 |alpha| sa[i] sb[j] sum_g max_{k in g} |qa[i,k]| * max_{k in g} |qb[k,j]|
+    7 * 2^-13 |alpha| sa[i] sb[j] sum_g max_{k in g} |qa[i,k]| * max_{k in g} |qb[k,j]|
     (the product of the group maxima bounds the group's largest product).
     qa: M x K codes, qb: K x N codes, groups of eight k from k = 0."""
     import oracle

@@ -64,15 +64,24 @@ def _requests(n, seed, lo=17, hi=700):
 def test_alone_and_in_the_mix_are_bitwise_equal_and_correct():
     import torch
     import paper_1902_10345_amd as mm
-    reqs = _requests(40, seed=9)
+    # a large request first (its step copies 48 MB of operands, milliseconds
+    # of work), then 40 small ones submitted while that step is on the device:
+    # they are admitted into further steps on the other streams
+    n = 2048
+    big = (n, n, n, si.uniform((n, n), 91), si.uniform((n, n), 92), si.uniform((n, n), 93))
+    reqs = [big] + _requests(40, seed=9)
     arena, srv = _server(mm, 1 << 30)
     try:
-        bufs, tickets = [], []
+        bufs = []
         for (M, N, K, A, B, C0) in reqs:
             hA, hB, hC0 = _pinned(A), _pinned(B), _pinned(C0)
             hC = torch.empty((M, N), dtype=torch.float32, pin_memory=True)
             bufs.append((hA, hB, hC0, hC))
+        tickets = []
+        for i, ((M, N, K, _, _, _), (hA, hB, hC0, hC)) in enumerate(zip(reqs, bufs)):
             tickets.append(mm.server_submit(srv, M, N, K, 1.5, hA, hB, 0.5, hC0, hC))
+            if i == 0:
+                time.sleep(0.001)  # the large request's step is launched first
         _wait(mm, srv, tickets)
         st = mm.server_stats(srv)
         assert st["completed"] == len(reqs)
@@ -246,13 +255,17 @@ def test_queue_timeout_drops_stale_requests():
     import paper_1902_10345_amd as mm
     arena, srv = _server(mm, 1 << 26, slots=4, streams=2)
     try:
-        mm.server_set_queue_timeout(srv, 1.0)
+        mm.server_set_queue_timeout(srv, 0.2)
         A = torch.ones((32, 32), pin_memory=True)
         hC = torch.full((32, 32), -1.0, pin_memory=True)
         hC2 = torch.empty((32, 32), pin_memory=True)
-        time.sleep(0.05)
-        stale = mm.server_submit(srv, 32, 32, 32, 1.0, A, A, 0.0, None, hC,
-                                 mm.server_now(srv) - 10.0)
+        # the server clock starts at 0 when the server is created and a
+        # negative stamp means "now": wait until a stamp 0.5 s in the past is
+        # a valid (non-negative) one
+        time.sleep(0.6)
+        stamp = mm.server_now(srv) - 0.5
+        assert stamp >= 0
+        stale = mm.server_submit(srv, 32, 32, 32, 1.0, A, A, 0.0, None, hC, stamp)
         fresh = mm.server_submit(srv, 32, 32, 32, 1.0, A, A, 0.0, None, hC2)
         assert _poll_status(mm, srv, stale) == mm.STATUS_TIMED_OUT
         assert _poll_status(mm, srv, fresh) == mm.STATUS_OK
