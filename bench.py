@@ -90,6 +90,33 @@ def _time_steps(fn, steps, warmup, torch):
     return block, per, wall
 
 
+def _time_graph(fn, launches, steps, torch):
+    """Capture `launches` calls of `fn` in one graph and time `steps` replays
+    with events; returns (ms per launch, per-replay list in ms per launch)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(launches):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1) / launches)
+    del g
+    return statistics.median(per), per
+
+
 def _stats(per):
     """Median and a 95% confidence interval of the median (order statistics)
     plus Tukey-fence outlier count, as in the paper's timing methodology."""
@@ -507,12 +534,22 @@ def main():
         args.no_grouped = args.no_serving = args.no_cpu_baseline = True
 
     # ---------------- the other paths --------------------------------------
-    def one(name, fn, fl, peak, peak_name):
+    def one(name, fn, fl, peak, peak_name, graph=False):
         _log("path: " + name)
-        ms_, per_, _ = _time_steps(fn, K_, W_, torch)
+        extra = {}
+        if graph:
+            # launches shorter than the host's per-call cost: time a captured
+            # graph of 20 launches (device time per launch), and report the
+            # per-call time of host-issued launches beside it
+            host_ms, _, _ = _time_steps(fn, K_, W_, torch)
+            ms_, per_ = _time_graph(fn, 20, K_, torch)
+            extra = {"timing": "hipGraph replay of 20 launches, per launch",
+                     "host_issued_ms": round(host_ms, 4)}
+        else:
+            ms_, per_, _ = _time_steps(fn, K_, W_, torch)
         tf = fl / (ms_ * 1e-3) / 1e12
         paths[name] = {"ms": round(ms_, 4), "tflops": round(tf, 1),
-                       "frac_" + peak_name: round(tf / peak, 4), **_stats(per_)}
+                       "frac_" + peak_name: round(tf / peak, 4), **_stats(per_), **extra}
 
     if not args.headline_only:
         Cf = C.clone()
@@ -597,10 +634,10 @@ def main():
         M4 = 256
         _, (A4, B4, C4) = _dev_inputs(M4, M4, M4, 1, torch)
         one("f32_256^3", lambda: mm.gemm_f32(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4),
-            2.0 * M4 ** 3, PEAK_FP32_VALU, "fp32_peak")
+            2.0 * M4 ** 3, PEAK_FP32_VALU, "fp32_peak", graph=True)
         one("3xbf16_n3_256^3",
             lambda: mm.gemm_f32_3xbf16(M4, M4, M4, 1.0, A4, M4, B4, M4, 0.0, C4, M4, 3),
-            2.0 * M4 ** 3, PEAK_BF16_MFMA, "bf16_peak")
+            2.0 * M4 ** 3, PEAK_BF16_MFMA, "bf16_peak", graph=True)
         del A4, B4, C4
         # one GPU's share of the 4096^3 product under eight-way row sharding
         M5 = 512
@@ -614,12 +651,12 @@ def main():
             lambda: mm.gemm_f32_3xbf16_splitk(M5, N, K, 1.5, A5, K, B5, N, 0.5, C5, N, 3, 0, ws5, nb5),
             2.0 * M5 * N * K, PEAK_BF16_MFMA, "bf16_peak")
         del A5, B5, C5
-        # a skinny product: 16 output tiles of 128 x 128, the reduction split 16 ways
+        # a skinny product (64 rows): one pass on the small-product tiles, and split-K
         M6 = 64
         _, (A6, B6, C6) = _dev_inputs(M6, N, K, 9, torch)
         one("3xbf16_n3_64x4096x4096",
             lambda: mm.gemm_f32_3xbf16(M6, N, K, 1.5, A6, K, B6, N, 0.5, C6, N, 3),
-            2.0 * M6 * N * K, PEAK_BF16_MFMA, "bf16_peak")
+            2.0 * M6 * N * K, PEAK_BF16_MFMA, "bf16_peak", graph=True)
         nb6 = mm.gemm_splitk_workspace_bytes(M6, N, K, 0)
         ws6 = torch.empty(max(nb6, 256), dtype=torch.uint8, device="cuda")
         one("3xbf16_n3_64x4096x4096_splitk%d" % mm.gemm_splitk_default_splits(M6, N, K),

@@ -169,7 +169,23 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   const int64_t cus = num_cus();
   auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
   const int64_t big = tiles(256, 256);
-  if (n_products == 6) return big >= cus ? 4 : 5;
+  (void)K;
+  // Shapes whose 128 x 128 tiles leave CUs idle: the small-product tiles (the
+  // k range split over a workgroup's eight waves), measured by graph replay
+  // over 19 shapes: 32 x 32 tiles up to two per CU (256^3: 3.7 us against
+  // 6.1 for the 64 x 64 LDS tile; 512^3 5.0 against 9.6), 64 x 64 tiles
+  // while those stay below two per CU (768^3, 1024^3), the 64 x 64 LDS tile
+  // beyond.
+  auto small = [&](int p3_32, int p3_64, int lds64) {
+    if (tiles(32, 32) <= 2 * cus) return p3_32;
+    return tiles(64, 64) < 2 * cus ? p3_64 : lds64;
+  };
+  if (n_products == 6) {
+    if (big >= cus) return 4;
+    // six products: the small-product tiles beat the 128 x 128 LDS tile on
+    // every underfilled shape swept but one (1536^2 x 512, 3 % behind)
+    return tiles(128, 128) >= cus ? 5 : small(11, 12, 12);
+  }
   // 256 x 256 x 16: 1.5-2.4 % ahead of the 32-deep slabs at 4096^3,
   // 8192 x 2048 x 4096 and 8192^2 x 4096 (same box, alternating)
   if (big >= cus) return 0;
@@ -178,13 +194,11 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   // the machine (4096 x 2048^2, 2560^3, 2048 x 4096^2; with and without
   // beta); 128 x 128 x 16 tiles while they fill every CU (at one tile per CU
   // they win by 6 % with beta == 0, the paper's C = A*B at 2048^3, and lose
-  // by 4 % with beta != 0); 64 x 64 tiles below that.
-  (void)K;
+  // by 4 % with beta != 0); the small-product tiles below that.
   const int64_t mid = tiles(256, 128);
   if (mid * 4 >= cus * 3 && mid <= cus) return 2;
-  const int64_t small = tiles(128, 128);
-  if (small >= cus) return 8;
-  return 6;
+  if (tiles(128, 128) >= cus) return 8;
+  return small(9, 10, 6);
 }
 
 gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
@@ -247,7 +261,11 @@ int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, in
   if (M <= 64 && N <= 64) return n_products == 6 ? 5 : 6;
   // M stacked batch times (saturated: only the tile count's size matters)
   const int64_t stacked = M <= 0 ? 0 : batch > ((int64_t)1 << 40) / M ? ((int64_t)1 << 40) : M * batch;
-  return bx3_default_config(stacked, N, K, n_products);
+  const int cfg = bx3_default_config(stacked, N, K, n_products);
+  // the small-product tiles have no batched variant: their LDS-staged
+  // counterparts of the same width take the batch
+  if (cfg >= 9) return n_products == 6 ? 5 : 6;
+  return cfg;
 }
 
 gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,

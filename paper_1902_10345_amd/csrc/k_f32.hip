@@ -268,12 +268,16 @@ const TileConfig &f32_config(int i) { return kF32Configs[i]; }
 int f32_default_config(int64_t M, int64_t N, int64_t K) {
   (void)K;
   // measured: the FP32 matrix-core tiles win while they fill every CU (256 x
-  // 256: 140 TFLOP/s at 4096^3 against 90 on the vector ALU); below that the
-  // 64 x 64 vector-ALU tile, which fills the machine with more workgroups
+  // 256: 140 TFLOP/s at 4096^3 against 90 on the vector ALU).  Below that the
+  // small-product tiles (the k range split over a workgroup's eight waves)
+  // win on every shape swept, 1.7-4.3x over the 64 x 64 vector-ALU tile
+  // (256^3: 4.1 against 17.5 us; graph-replayed launches): 64 x 64 tiles
+  // once they fill the CUs, 32 x 32 tiles before.
   const int64_t cus = num_cus();
-  if (((M + 255) / 256) * ((N + 255) / 256) >= cus) return 5;
-  if (((M + 127) / 128) * ((N + 127) / 128) >= cus) return 6;
-  return 1;
+  auto tiles = [&](int64_t b) { return ((M + b - 1) / b) * ((N + b - 1) / b); };
+  if (tiles(256) >= cus) return 5;
+  if (tiles(128) >= cus) return 6;
+  return tiles(64) >= cus ? 8 : 7;
 }
 
 gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {

@@ -333,3 +333,22 @@ def test_default_config_of_empty_shapes():
         for shape in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (0, 0, 0)]:
             c = mm.gemm_default_config(path, *shape)
             assert 0 <= c < mm.gemm_num_configs(path), (path, shape, c)
+
+
+def test_default_tile_rules_for_underfilled_shapes():
+    """Shapes whose 128 x 128 tiles leave compute units idle take the small-
+    product tiles (k range split over a workgroup's waves); machine-filling
+    shapes keep the LDS-staged matrix-core tiles (256 compute units)."""
+    import paper_1902_10345_amd as mm
+
+    def name(path, M, N, K):
+        return mm.gemm_config_name(path, mm.gemm_default_config(path, M, N, K))
+    assert name(mm.PATH_F32, 256, 256, 256) == "f32_small_32x32_8wk"
+    assert name(mm.PATH_3XBF16, 256, 256, 256) == "bx3_small_32x32_8wk_p3"
+    assert name(mm.PATH_F32, 1024, 1024, 1024) == "f32_small_64x64_8wk"
+    assert name(mm.PATH_3XBF16, 1024, 1024, 1024) == "bx3_small_64x64_8wk_p3"
+    assert name(mm.PATH_3XBF16, 64, 4096, 4096) == "bx3_small_32x32_8wk_p3"
+    assert name(mm.PATH_3XBF16, 1536, 1536, 512) == "bx3_64x64x32_4w32x32_p3"
+    assert name(mm.PATH_F32, 2048, 2048, 2048) == "f32mfma_128x128x16_4w64x64"
+    assert name(mm.PATH_F32, 4096, 4096, 4096) == "f32mfma_256x256x16_8w128x64"
+    assert name(mm.PATH_3XBF16, 4096, 4096, 4096) == "bx3_256x256x16_8w128x64_p3"
