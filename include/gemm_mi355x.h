@@ -124,6 +124,25 @@ gemm_status gemm_f32_3xbf16_splitk(int64_t M, int64_t N, int64_t K, float alpha,
                                    int splits, void *workspace, size_t ws_bytes,
                                    hipStream_t stream);
 
+/* The split-K product above for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument; the partial planes live in a fixed
+ * device array of GEMM_NOALLOC_SCRATCH_BYTES bytes inside the library, one
+ * copy per device, held until the process ends and resolved on the first
+ * call with that device current.  No device memory is allocated or freed by
+ * the call.  Every call on one device shares that device's array, so calls
+ * that overlap on one device race: serialise them (one stream).  Results are
+ * bitwise those of gemm_f32_3xbf16_splitk with the same split count.
+ * Arguments: 1..13 as gemm_f32_3xbf16_splitk, 14 stream.  Returns
+ * GEMM_STATUS_NO_MEMORY, with nothing enqueued, when splits * M * N * 4
+ * bytes (after resolving splits = 0 to the default; 0 bytes when the count
+ * resolves to 1) exceed GEMM_NOALLOC_SCRATCH_BYTES. */
+#define GEMM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gemm_status gemm_f32_3xbf16_splitk_noalloc(int64_t M, int64_t N, int64_t K, float alpha,
+                                           const float *A, int64_t lda, const float *B,
+                                           int64_t ldb, float beta, float *C, int64_t ldc,
+                                           int n_products, int splits, hipStream_t stream);
+
 /* The staging split alone, for verification: x (n floats, device) ->
  * planes p0, p1, p2 (n bfloat16 bit patterns each, device; p2 may be NULL).
  * Arguments: 1 n, 2 x, 3 p0, 4 p1, 5 p2, 6 stream. */

@@ -67,6 +67,8 @@ _sig("gemm_splitk_default_splits", _int, _i64, _i64, _i64)
 _sig("gemm_splitk_workspace_bytes", _sz, _i64, _i64, _i64, _int)
 _sig("gemm_f32_3xbf16_splitk", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64,
      _int, _int, _vp, _sz, _vp)
+_sig("gemm_f32_3xbf16_splitk_noalloc", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp,
+     _i64, _int, _int, _vp)
 _sig("split_bf16x3", _int, _i64, _vp, _vp, _vp, _vp, _vp)
 _sig("gemm_fp8_workspace_bytes", _sz, _i64, _i64, _i64)
 _sig("gemm_fp8_scaled", _int, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32, _vp, _i64, _vp,
@@ -190,6 +192,18 @@ def gemm_f32_3xbf16_splitk(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_produ
     return check(lib.gemm_f32_3xbf16_splitk(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta, ptr(C),
                                             ldc, n_products, splits, ptr(workspace), ws_bytes,
                                             stream_handle(stream)))
+
+
+# GEMM_NOALLOC_SCRATCH_BYTES of the header: the fixed scratch of the
+# no-allocation split-K entry point
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def gemm_f32_3xbf16_splitk_noalloc(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, n_products=3,
+                                   splits=0, stream=None):
+    return check(lib.gemm_f32_3xbf16_splitk_noalloc(M, N, K, alpha, ptr(A), lda, ptr(B), ldb, beta,
+                                                    ptr(C), ldc, n_products, splits,
+                                                    stream_handle(stream)))
 
 
 def split_bf16x3(n, x, p0, p1, p2=None, stream=None):
