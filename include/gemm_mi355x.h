@@ -64,10 +64,14 @@ const char *gemm_version(void);
 /* ------------------------------------------------------------------------
  * Plain FP32 path: binary32 products and binary32 sums, no split.
  * C <- alpha*A*B + beta*C.  The library picks the tile configuration per
- * shape (gemm_default_config): where its tiles fill the compute units the
- * binary32 matrix-core tile (v_mfma_f32_32x32x2_f32: each product and sum in
- * binary32), otherwise a vector-ALU tile with fused multiply-add accumulation
- * in per-lane register micro-tiles; gemm_run_config selects either kind.
+ * shape (gemm_default_config): where 256 x 256 or 128 x 128 tiles fill the
+ * compute units, the binary32 matrix-core tile (v_mfma_f32_32x32x2_f32: each
+ * product and sum in binary32); below that the small-product tiles (32 x 32
+ * or 64 x 64 outputs per workgroup, the k range split over its eight waves
+ * on the same matrix-core instruction, partial tiles summed in wave order).
+ * The vector-ALU tiles (fused multiply-add accumulation in per-lane register
+ * micro-tiles) remain configurations of the path: gemm_run_config selects
+ * any of them.
  * Tiling of the (i,j) map, LDS staging of A/B tiles with double buffering and
  * register micro-tiles realise the MapTiling, LocalStorage, DoubleBuffering
  * and Vectorization steps of the paper's transformation chain (Sec. 6.2,
