@@ -78,7 +78,7 @@ __device__ __forceinline__ int swz(int r) {
   else return 0;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, int ST = 2>
 struct Cfg {
   static constexpr int NT = 64 * NW;          // lanes per workgroup
   static constexpr int WAVES_M = BM / WM;
@@ -97,7 +97,8 @@ struct Cfg {
   static constexpr int PLANE_A = BM * BK;     // bf16 elements per A plane
   static constexpr int PLANE_B = BN * BK;
   static constexpr int STAGE = NPL * (PLANE_A + PLANE_B);  // bf16 units per stage
-  static constexpr int LDS_BYTES = 2 * STAGE * 2;
+  static constexpr int STAGES = ST;           // LDS stages (2, or a ring of 3)
+  static constexpr int LDS_BYTES = ST * STAGE * 2;
   // Register sets for slabs in flight: with BK >= 32 one slab's MFMA work
   // (2 k-steps) already covers the load latency, so one set is kept and the
   // registers go to fragments; BK = 16 keeps two sets.
@@ -279,13 +280,15 @@ struct Stage {
 // unpredicated load path; edge slabs take a guarded path that reads zeros
 // outside the matrices.  The choice is uniform across the workgroup.
 template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA,
-          bool TA = false, bool TB = false>
+          bool TA = false, bool TB = false, int ST = 2>
 __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
                                      const float *__restrict__ A, int64_t lda,
                                      const float *__restrict__ B, int64_t ldb, float beta,
                                      float *__restrict__ C, int64_t ldc, int m0, int n0,
                                      __bf16 *lds) {
-  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW, ST>;
+  static_assert(ST == 2 || (ST == 3 && NP == 2 && BK == 16),
+                "the three-stage ring is built for 16-deep slabs of three products");
   constexpr int NT = G::NT;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -514,6 +517,163 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       sstore(S0{}, 0);
       __syncthreads();
     }
+  } else if constexpr (ST == 3) {
+    // Three LDS stages in a ring, two register sets, one 16-deep k-step per
+    // slab.  Step s multiplies slab s from stage s%3.  The fragments of its
+    // first product (a1 * b0) were read during step s-1, so its MFMAs issue
+    // right after the barrier while the reads of a0 and b1 are in flight.
+    // In the same step slab s+2 (loaded from global memory in step s-1, in
+    // register set s%2) is split and written to stage (s+2)%3, the loads of
+    // slab s+3 go to the other set, and the first-product fragments of slab
+    // s+1 are read from stage (s+1)%3 into the other fragment set.  One
+    // barrier per step: it orders the writes of slab s+2 before their first
+    // reads (step s+1) and the last reads of stage s%3 (this step) before it
+    // is rewritten with slab s+3 (step s+1).
+    using Fr = Frags;
+    using First = std::true_type;
+    using Rest = std::false_type;
+    auto rd = [&](Fr &f, int stage, auto FIRST) {
+      const __bf16 *sA = lds + stage * G::STAGE;
+      const __bf16 *sB = sA + G::NPL * G::PLANE_A;
+      const int c = lgrp;
+      constexpr int pa = decltype(FIRST)::value ? 1 : 0, pb = decltype(FIRST)::value ? 0 : 1;
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        const int n = wn0 + j * 32 + lrow;
+        f.b[pb][j] = *reinterpret_cast<const bf16x8 *>(sB + pb * G::PLANE_B + n * BK +
+                                                       ((c ^ swz<BK>(n)) << 3));
+      }
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i) {
+        const int r = wm0 + i * 32 + lrow;
+        f.a[pa][i] = *reinterpret_cast<const bf16x8 *>(sA + pa * G::PLANE_A + r * BK +
+                                                       ((c ^ swz<BK>(r)) << 3));
+      }
+    };
+    auto prod = [&](const Fr &f, int pa, int pb) {
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[pa][i], f.b[pb][j], acc[i][j],
+                                                              0, 0, 0);
+    };
+    // One fragment of a set: idx < FN the B block idx, else the A block
+    // idx - FN, of the planes of the first product (a1, b0) or of the rest
+    // (a0, b1).
+    auto rd_one = [&](Fr &f, int stage, auto FIRST, auto IDX) {
+      constexpr int idx = decltype(IDX)::value;
+      constexpr int pa = decltype(FIRST)::value ? 1 : 0, pb = decltype(FIRST)::value ? 0 : 1;
+      const __bf16 *sA = lds + stage * G::STAGE;
+      const __bf16 *sB = sA + G::NPL * G::PLANE_A;
+      const int c = lgrp;
+      if constexpr (idx < G::FN) {
+        const int n = wn0 + idx * 32 + lrow;
+        f.b[pb][idx] = *reinterpret_cast<const bf16x8 *>(sB + pb * G::PLANE_B + n * BK +
+                                                         ((c ^ swz<BK>(n)) << 3));
+      } else {
+        const int r = wm0 + (idx - G::FN) * 32 + lrow;
+        f.a[pa][idx - G::FN] = *reinterpret_cast<const bf16x8 *>(sA + pa * G::PLANE_A + r * BK +
+                                                                 ((c ^ swz<BK>(r)) << 3));
+      }
+    };
+    constexpr int kBlk = G::FM * G::FN;
+    constexpr int kMfma = 3 * kBlk;               // a1*b0, a0*b1, a0*b0
+    constexpr int kHalf = G::FM + G::FN;          // fragments per plane pair
+    constexpr int kItems = SA::ITEMS + SB::ITEMS;
+    static_assert(kHalf <= 2 * kBlk && 4 * kItems <= kBlk, "the step's work fits its MFMA slots");
+    // MFMA q of a step: product q / kBlk, block q % kBlk
+    auto mfma_one = [&](const Fr &f, auto Q) {
+      constexpr int q = decltype(Q)::value;
+      constexpr int pr = q / kBlk, bi = (q % kBlk) / G::FN, bj = q % G::FN;
+      constexpr int pa = pr == 0 ? 1 : 0, pb = pr == 1 ? 1 : 0;
+      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[pa][bi], f.b[pb][bj], acc[bi][bj],
+                                                            0, 0, 0);
+    };
+    // split of value pair E of item IT (A items first) from register set SS,
+    // and the item's LDS writes with its last pair
+    bf16x8 sp0, sp1;
+    auto split_pair = [&](auto SS, int stage, auto IT, auto E) {
+      constexpr int set = decltype(SS)::value;
+      constexpr int it = decltype(IT)::value, e = 2 * decltype(E)::value;
+      const float *x;
+      if constexpr (it < SA::ITEMS) x = sa.r[set][it];
+      else x = sb.r[set][it - SA::ITEMS];
+      bf16x2 x0, x1;
+      split2(f32x2{x[e], x[e + 1]}, x0, x1);
+      sp0[e] = x0.x; sp0[e + 1] = x0.y;
+      sp1[e] = x1.x; sp1[e + 1] = x1.y;
+      if constexpr (e == 6) {
+        __bf16 *sA = lds + stage * G::STAGE;
+        __bf16 *base = it < SA::ITEMS ? sA : sA + G::NPL * G::PLANE_A;
+        constexpr int PLANE = it < SA::ITEMS ? G::PLANE_A : G::PLANE_B;
+        const int idx = tid + NT * (it < SA::ITEMS ? it : it - SA::ITEMS);
+        const int rr = it < SA::ITEMS ? SA::row_of(idx) : SB::row_of(idx);
+        const int cc = it < SA::ITEMS ? SA::chunk_of(idx) : SB::chunk_of(idx);
+        const int off = rr * BK + ((cc ^ swz<BK>(rr)) << 3);
+        *reinterpret_cast<bf16x8 *>(base + off) = sp0;
+        *reinterpret_cast<bf16x8 *>(base + PLANE + off) = sp1;
+      }
+    };
+    // LS: register set receiving slab s+3; SS: set holding slab s+2; fc:
+    // fragments of slab s (a1, b0 already read); fn: receives the a1, b0
+    // fragments of slab s+1 (after a0 * b1, while a0 * b0 still needs fc.b0).
+    // The step's other work sits between its MFMAs in a fixed order (a
+    // scheduling barrier after each slot): the reads of a0 and b1 first, the
+    // global loads, the split and LDS writes of slab s+2 during a0 * b1's
+    // predecessor slots, the first-product reads of slab s+1 last.
+    auto step = [&](auto LS, auto SS, int kload, int st, Fr &fc, Fr &fn) {
+      const int st1 = st == 2 ? 0 : st + 1, st2 = st1 == 2 ? 0 : st1 + 1;
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<kMfma>([&](auto Q) {
+        constexpr int m = decltype(Q)::value;
+        if constexpr (2 * m < kHalf) {
+          rd_one(fc, st, Rest{}, std::integral_constant<int, 2 * m>{});
+          if constexpr (2 * m + 1 < kHalf) rd_one(fc, st, Rest{}, std::integral_constant<int, 2 * m + 1>{});
+        }
+        mfma_one(fc, Q);
+        constexpr int kLoad0 = (kHalf + 1) / 2;
+        if constexpr (m >= kLoad0 && m < kLoad0 + SA::ITEMS)
+          sa.template load_item<decltype(LS)::value>(m - kLoad0, kload);
+        else if constexpr (m >= kLoad0 + SA::ITEMS && m < kLoad0 + kItems)
+          sb.template load_item<decltype(LS)::value>(m - kLoad0 - SA::ITEMS, kload);
+        constexpr int kSplit0 = kBlk;
+        if constexpr (m >= kSplit0 && m < kSplit0 + 4 * kItems)
+          split_pair(SS, st2, std::integral_constant<int, (m - kSplit0) / 4>{},
+                     std::integral_constant<int, (m - kSplit0) % 4>{});
+        constexpr int kEarly0 = 2 * kBlk;
+        if constexpr (m >= kEarly0 && 2 * (m - kEarly0) < kHalf) {
+          rd_one(fn, st1, First{}, std::integral_constant<int, 2 * (m - kEarly0)>{});
+          if constexpr (2 * (m - kEarly0) + 1 < kHalf)
+            rd_one(fn, st1, First{}, std::integral_constant<int, 2 * (m - kEarly0) + 1>{});
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      __syncthreads();
+    };
+    Fr f0, f1;
+    // prologue: slab 0 is in stage 0 (above); slab 1 to stage 1, slab 2 in
+    // flight in set 0, the first-product fragments of slab 0 in registers
+    if (KT > 1) gload(S1{}, Fast{}, kslab(1));
+    else gload(S1{}, Masked{}, kbase);
+    sstore(S1{}, 1);
+    if (KT > 1) gload(S0{}, Fast{}, kslab(2));
+    else gload(S0{}, Masked{}, kbase);
+    __syncthreads();
+    rd(f0, 0, First{});
+    int st = 0;
+    for (; t + 2 <= KT; t += 2) {
+      step(S1{}, S0{}, kslab(t + 3), st, f0, f1);
+      st = st == 2 ? 0 : st + 1;
+      step(S0{}, S1{}, kslab(t + 4), st, f1, f0);
+      st = st == 2 ? 0 : st + 1;
+    }
+    if (t < KT) {  // odd slab count: the last slab, in stage st, a1 and b0 in f0
+      rd(f0, st, Rest{});
+      prod(f0, 1, 0);
+      prod(f0, 0, 1);
+      prod(f0, 0, 0);
+    }
   } else if constexpr (kDeep) {
     // One wave per SIMD (4 waves of 128 x 128): no other wave hides a stall,
     // so every latency is covered inside the wave.  Slab s is loaded from
@@ -684,7 +844,7 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       __syncthreads();
     }
   }
-  if constexpr (!kDeep) {
+  if constexpr (!kDeep && ST == 2) {
     if (t < KT) {  // odd slab count: the last slab sits in stage 0
       mfma_stage(0);
     }
@@ -703,21 +863,41 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
         C + (int64_t)m0 * ldc + n0, (short)0, (int)(((int64_t)(rowsC - 1) * ldc + colsC) * 4),
         kBufferFlags);
     const int ldc4 = (int)ldc * 4;
+    // With beta != 0 the reads of C for a group of blocks are all issued
+    // before the group's first store: a buffer load is never moved above a
+    // buffer store through the same resource, so a read-modify-write per
+    // element would wait out one memory round trip per element.
+    constexpr int kBlk = G::FM * G::FN;
+    constexpr int kGrp = kBlk < 4 ? kBlk : 4;
+    static_assert(kBlk % kGrp == 0, "whole groups of accumulator blocks");
 #pragma unroll
-    for (int i = 0; i < G::FM; ++i)
+    for (int g0 = 0; g0 < kBlk; g0 += kGrp) {
+      float cold[kGrp][16];
+      int vb[kGrp];
 #pragma unroll
-      for (int j = 0; j < G::FN; ++j) {
+      for (int q = 0; q < kGrp; ++q) {
+        const int i = (g0 + q) / G::FN, j = (g0 + q) % G::FN;
         const int col = wn0 + j * 32 + lrow;
-        const int vbase = col < colsC ? (wm0 + i * 32 + 4 * lgrp) * ldc4 + col * 4 : (int)0x80000000;
+        vb[q] = col < colsC ? (wm0 + i * 32 + 4 * lgrp) * ldc4 + col * 4 : (int)0x80000000;
+        if (BETA) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int soff = (8 * (e >> 2) + (e & 3)) * ldc4;
-          float v = alpha * acc[i][j][e];
-          if (BETA)
-            v = fmaf(beta, __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rC, vbase, soff, 0)), v);
-          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rC, vbase, soff, 0);
+          for (int e = 0; e < 16; ++e)
+            cold[q][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                       rC, vb[q], (8 * (e >> 2) + (e & 3)) * ldc4, 0));
         }
       }
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        const int i = (g0 + q) / G::FN, j = (g0 + q) % G::FN;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          float v = alpha * acc[i][j][e];
+          if (BETA) v = fmaf(beta, cold[q][e], v);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rC, vb[q],
+                                                (8 * (e >> 2) + (e & 3)) * ldc4, 0);
+        }
+      }
+    }
     return;
   }
 #pragma unroll

@@ -9,18 +9,18 @@ namespace mm {
 namespace bx3 {
 
 template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA, bool TA,
-          bool TB>
+          bool TB, int ST = 2>
 __global__ __launch_bounds__(64 * NW, 1) void gemm_bx3_kernel(
     int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda,
     const float *__restrict__ B, int64_t ldb, float beta, float *__restrict__ C, int64_t ldc,
     int tiles_m, int tiles_n) {
-  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW, ST>;
   __shared__ __attribute__((aligned(16))) __bf16 lds[G::LDS_BYTES / 2];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   int tm, tn;
   tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
-  tile<BM, BN, BK, WM, WN, NP, NW, VEC, BETA, TA, TB>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                      ldc, tm * BM, tn * BN, lds);
+  tile<BM, BN, BK, WM, WN, NP, NW, VEC, BETA, TA, TB, ST>(M, N, K, alpha, A, lda, B, ldb, beta,
+                                                          C, ldc, tm * BM, tn * BN, lds);
 }
 
 // The plain binary32 product on the FP32 matrix cores (v_mfma_f32_32x32x2f32):
@@ -90,7 +90,8 @@ gemm_status launch_f32mfma(const GemmArgs &g, hipStream_t s) {
   return check_launch("gemm_f32mfma_kernel");
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool TA = false, bool TB = false>
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool TA = false, bool TB = false,
+          int ST = 2>
 gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const int tiles_m = (int)((g.M + BM - 1) / BM);
   const int tiles_n = (int)((g.N + BN - 1) / BN);
@@ -104,7 +105,7 @@ gemm_status launch(const GemmArgs &g, hipStream_t s) {
   const bool beta = g.beta != 0.0f;
   dim3 grid((unsigned)nwg), block(64 * NW);
 #define MM_LAUNCH(V, BT)                                                                     \
-  hipLaunchKernelGGL((gemm_bx3_kernel<BM, BN, BK, WM, WN, NP, NW, V, BT, TA, TB>), grid,    \
+  hipLaunchKernelGGL((gemm_bx3_kernel<BM, BN, BK, WM, WN, NP, NW, V, BT, TA, TB, ST>), grid, \
                      block, 0, s, (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.B,     \
                      g.ldb, g.beta, g.C, g.ldc, tiles_m, tiles_n)
   if constexpr (!TA || TB) {

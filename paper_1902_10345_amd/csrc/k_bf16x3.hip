@@ -159,6 +159,9 @@ static const Bx3Config kBx3Configs[] = {
     {{64, 64, 16, "bx3_small_64x64_8wk_p3"}, 2},
     {{32, 32, 16, "bx3_small_32x32_8wk_p6"}, 3},
     {{64, 64, 16, "bx3_small_64x64_8wk_p6"}, 3},
+    // the 256 x 256 x 16 tile with a ring of three LDS stages: the first
+    // product's fragments of the next slab are read before the barrier
+    {{256, 256, 16, "bx3_256x256x16_8w128x64_p3_ring3"}, 2},
 };
 
 int bx3_num_configs() { return (int)(sizeof(kBx3Configs) / sizeof(kBx3Configs[0])); }
@@ -214,6 +217,7 @@ gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 6: return bx3::launch<64, 64, 32, 32, 32, 2, 4>(g, s);
     case 7: return bx3::launch<256, 256, 16, 128, 128, 2, 4>(g, s);
     case 8: return bx3::launch<128, 128, 16, 64, 64, 2, 4>(g, s);
+    case 13: return bx3::launch<256, 256, 16, 128, 64, 2, 8, false, false, 3>(g, s);
     default: set_error("gemm_f32_3xbf16: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

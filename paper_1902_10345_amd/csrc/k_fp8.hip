@@ -389,6 +389,88 @@ struct Fp8Cfg {
 
 __device__ __forceinline__ int swz8(int r) { return (r ^ (r >> 3)) & 7; }
 
+// Epilogue of both FP8 kernels: C <- (sa[i] * (sb[j] * alpha)) * acc + beta * C
+// over the wave's FM x FN blocks of 32 x 32.  Through buffer resources over
+// the tile's valid part of C and of the scale vectors (rows and columns past
+// the matrix read as zero and their stores are dropped), one block row at a
+// time: its scales and, with beta != 0, its C values are all loaded before
+// its first store (a buffer load is never moved above a buffer store through
+// the same resource, so a read-modify-write per element would wait out one
+// memory round trip per element).  A C row stride too large for 32-bit
+// offsets takes the element-wise path.
+template <int FM, int FN, int BM, int BN, bool BETA>
+__device__ __forceinline__ void epilogue(const f32x16 (&acc)[FM][FN], int Mr, int Nr, int m0,
+                                         int n0, int wm0, int wn0, int lrow, int lgrp,
+                                         float alpha, const float *__restrict__ sa,
+                                         const float *__restrict__ sb, float beta,
+                                         float *__restrict__ C, int64_t ldc) {
+  const int rowsC = Mr < BM ? Mr : BM, cols = Nr < BN ? Nr : BN;
+  if ((int64_t)BM * ldc * 4 < ((int64_t)1 << 31)) {
+    const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc(
+        C + (int64_t)m0 * ldc + n0, (short)0, (int)(((int64_t)(rowsC - 1) * ldc + cols) * 4),
+        kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rSa = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(sa + m0), (short)0, rowsC * 4, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rSb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(sb + n0), (short)0, cols * 4, kBufferFlags);
+    const int ldc4 = (int)ldc * 4;
+    float sj[FN];
+    int vb[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = wn0 + j * 32 + lrow;
+      const bool in = col < cols;
+      sj[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                            rSb, in ? col * 4 : (int)0x80000000, 0, 0)) * alpha;
+      vb[j] = in ? col * 4 : (int)0x80000000;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int r0 = wm0 + i * 32 + 4 * lgrp;  // row of element 0; element e adds 8(e/4) + e%4
+      float si[16], cold[FN][16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        si[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                              rSa, (r0 + 8 * (e >> 2) + (e & 3)) * 4, 0, 0));
+      if (BETA) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int e = 0; e < 16; ++e)
+            cold[j][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                       rC, vb[j], (r0 + 8 * (e >> 2) + (e & 3)) * ldc4, 0));
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          float v = (si[e] * sj[j]) * acc[i][j][e];
+          if (BETA) v = fmaf(beta, cold[j][e], v);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rC, vb[j],
+                                                (r0 + 8 * (e >> 2) + (e & 3)) * ldc4, 0);
+        }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = wn0 + j * 32 + lrow;
+      if (col >= Nr) continue;
+      const float sj = sb[n0 + col] * alpha;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
+        if (row < Mr) {
+          float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
+          const float v = (sa[m0 + row] * sj) * acc[i][j][e];
+          *p = BETA ? fmaf(beta, *p, v) : v;
+        }
+      }
+    }
+}
+
 template <int BM, int BN, int WM, int WN, bool BETA>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_kernel(
     int M, int N, int64_t Kp, float alpha, const uint8_t *__restrict__ qa,
@@ -521,23 +603,8 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_kernel
     mfma_step(0, 1);
   }
 
-#pragma unroll
-  for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const int col = wn0 + j * 32 + lrow;
-      if (col >= Nr) continue;
-      const float sj = sb[n0 + col] * alpha;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
-        if (row < Mr) {
-          float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
-          const float v = (sa[m0 + row] * sj) * acc[i][j][e];
-          *p = BETA ? fmaf(beta, *p, v) : v;
-        }
-      }
-    }
+  epilogue<G::FM, G::FN, BM, BN, BETA>(acc, Mr, Nr, m0, n0, wm0, wn0, lrow, lgrp, alpha, sa, sb,
+                                        beta, C, ldc);
 }
 
 // Same tile, MFMA and epilogue, but the operand codes go from HBM straight
@@ -665,23 +732,8 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_dma_ke
     mfma_step(st0, 1);
   }
 
-#pragma unroll
-  for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const int col = wn0 + j * 32 + lrow;
-      if (col >= Nr) continue;
-      const float sj = sb[n0 + col] * alpha;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = wm0 + i * 32 + 8 * (e >> 2) + 4 * lgrp + (e & 3);
-        if (row < Mr) {
-          float *p = C + (int64_t)(m0 + row) * ldc + (n0 + col);
-          const float v = (sa[m0 + row] * sj) * acc[i][j][e];
-          *p = BETA ? fmaf(beta, *p, v) : v;
-        }
-      }
-    }
+  epilogue<G::FM, G::FN, BM, BN, BETA>(acc, Mr, Nr, m0, n0, wm0, wn0, lrow, lgrp, alpha, sa, sb,
+                                        beta, C, ldc);
 }
 
 // Raw conversion, for verification of the encoder.
@@ -839,13 +891,14 @@ static gemm_status fp8_launch(int64_t M, int64_t N, const fp8::Layout &L, float 
   return check_launch("gemm_fp8_kernel");
 }
 
-int fp8_num_configs() { return 5; }
+int fp8_num_configs() { return 6; }
 const char *fp8_config_name(int cfg) {
   switch (cfg) {
     case 0: return "fp8_256x256x128_8w128x64";
     case 1: return "fp8_256x256x128_4w128x128";
     case 3: return "fp8_128x128x128_4w64x64_dma";
     case 4: return "fp8_256x128x128_8w64x64_dma";
+    case 5: return "fp8_256x256x128_4w128x128_dma";
     default: return "fp8_256x256x128_8w128x64_dma";
   }
 }
@@ -858,6 +911,7 @@ gemm_status fp8_gemm_run_cfg(int64_t M, int64_t N, int64_t K, float alpha, const
   if (cfg == 2) return fp8_launch<256, 256, 128, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
   if (cfg == 3) return fp8_launch<128, 128, 64, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
   if (cfg == 4) return fp8_launch<256, 128, 64, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
+  if (cfg == 5) return fp8_launch<256, 256, 128, 128, true>(M, N, L, alpha, base, beta, C, ldc, s);
   return fp8_launch<256, 256, 128, 64, false>(M, N, L, alpha, base, beta, C, ldc, s);
 }
 

@@ -93,6 +93,19 @@ def test_every_config():
         _check(A, B, C0, C, 1.5, 0.5, n)
 
 
+@pytest.mark.parametrize("K", [16, 32, 48, 64, 80, 130, 1000])
+def test_ring_config_every_slab_count_parity(K):
+    """The 256 x 256 x 16 tile with a ring of three LDS stages: one to four
+    slabs (prologue only, one loop pass, loop plus odd tail), a partial first
+    slab, ragged M and N edges."""
+    import paper_1902_10345_amd as mm
+    cfg = [c for c in range(mm.gemm_num_configs(mm.PATH_3XBF16))
+           if mm.gemm_config_name(mm.PATH_3XBF16, c) == "bx3_256x256x16_8w128x64_p3_ring3"][0]
+    M, N = 300, 520
+    A, B, C0, _, C = _run(mm, M, N, K, 1.5, 0.5, 3, seed=K + 5, cfg=cfg)
+    _check(A, B, C0, C, 1.5, 0.5, 3)
+
+
 def test_mismatched_products_for_config_is_rejected():
     import paper_1902_10345_amd as mm
     cfg6 = [c for c in range(mm.gemm_num_configs(mm.PATH_3XBF16))
