@@ -78,7 +78,7 @@ __device__ __forceinline__ int swz(int r) {
   else return 0;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, int ST = 2>
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, int ST = 2, int SETS_ = 0>
 struct Cfg {
   static constexpr int NT = 64 * NW;          // lanes per workgroup
   static constexpr int WAVES_M = BM / WM;
@@ -102,7 +102,7 @@ struct Cfg {
   // Register sets for slabs in flight: with BK >= 32 one slab's MFMA work
   // (2 k-steps) already covers the load latency, so one set is kept and the
   // registers go to fragments; BK = 16 keeps two sets.
-  static constexpr int SETS = BK >= 32 ? 1 : 2;
+  static constexpr int SETS = SETS_ ? SETS_ : (BK >= 32 ? 1 : 2);
 };
 
 // Staging of one operand slab into LDS: ROWS LDS rows (the rows of A's tile
@@ -280,13 +280,13 @@ struct Stage {
 // unpredicated load path; edge slabs take a guarded path that reads zeros
 // outside the matrices.  The choice is uniform across the workgroup.
 template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA,
-          bool TA = false, bool TB = false, int ST = 2>
+          bool TA = false, bool TB = false, int ST = 2, int SETS_ = 0>
 __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
                                      const float *__restrict__ A, int64_t lda,
                                      const float *__restrict__ B, int64_t ldb, float beta,
                                      float *__restrict__ C, int64_t ldc, int m0, int n0,
                                      __bf16 *lds) {
-  using G = Cfg<BM, BN, BK, WM, WN, NP, NW, ST>;
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW, ST, SETS_>;
   static_assert(ST == 2 || (ST == 3 && NP == 2 && BK == 16),
                 "the three-stage ring is built for 16-deep slabs of three products");
   constexpr int NT = G::NT;
@@ -784,9 +784,11 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
       __syncthreads();
     }
     if (t < KT) frag_mfma(f0);  // odd slab count: the last slab is in f0
-  } else if constexpr (NP == 1) {
-    // FP32 mode, two register sets: 64 MFMAs per wave and slab leave the
-    // loads and stores plenty of room; the compiler schedules them.
+  } else if constexpr (NP == 1 || G::KS == 2) {
+    // Two register sets with two k-steps per slab (the FP32 mode, whose 64
+    // MFMAs per wave and slab leave the loads and stores plenty of room, and
+    // 32-deep split slabs with their loads issued two slabs ahead): the
+    // compiler schedules the loads and stores around the MFMAs.
     if (KT > 1) gload(S1{}, Fast{}, kslab(1));
     else gload(S1{}, Masked{}, kbase);
     __syncthreads();
