@@ -736,6 +736,151 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_dma_ke
                                         beta, C, ldc);
 }
 
+// The direct-to-LDS tile with 64-deep slabs in a ring of four LDS stages:
+// the DMA of slab t+3 is issued once slab t has landed in every wave, so three
+// slabs are in flight while one is multiplied (the two-stage kernel above has
+// one).  LDS rows are 64 bytes (64 codes); a wave's DMA fills 1024 contiguous
+// bytes, 16 rows, lane l at byte 16 l; the chunk swizzle (r >> 2) & 3 makes each
+// group of 16 consecutive rows read at one logical chunk cover the 64 banks
+// once.  One MFMA k-step (64 codes) per slab and stage.
+__device__ __forceinline__ int swz4(int r) { return (r >> 2) & 3; }
+
+template <int BM, int BN, int WM, int WN, bool BETA>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void gemm_fp8_ring_kernel(
+    int M, int N, int64_t Kp, float alpha, const uint8_t *__restrict__ qa,
+    const uint8_t *__restrict__ qbT, const float *__restrict__ sa, const float *__restrict__ sb,
+    float beta, float *__restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+  constexpr int BK = 64, NST = 4;
+  constexpr int NT = 64 * (BM / WM) * (BN / WN), NW = NT / 64, WAVES_N = BN / WN;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int STAGE = (BM + BN) * BK;
+  constexpr int A_CH = BM * BK / 16 / NT, B_CH = BN * BK / 16 / NT;  // DMA blocks per wave and slab
+  static_assert(A_CH * NT * 16 == BM * BK && B_CH * NT * 16 == BN * BK, "whole DMA blocks per wave");
+  // four arrays rather than one: the compiler then knows which stage each
+  // DMA writes and each fragment read reads, and waits only for the DMA of
+  // the stage being read (one array would make every read wait for all)
+  __shared__ __attribute__((aligned(1024))) uint8_t st0[STAGE];
+  __shared__ __attribute__((aligned(1024))) uint8_t st1[STAGE];
+  __shared__ __attribute__((aligned(1024))) uint8_t st2[STAGE];
+  __shared__ __attribute__((aligned(1024))) uint8_t st3[STAGE];
+  static_assert(NST == 4, "four stage arrays");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int Mr = M - m0, Nr = N - n0;
+  const int rowsA = Mr < BM ? Mr : BM, rowsB = Nr < BN ? Nr : BN;
+  const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(qa + (int64_t)m0 * Kp), (short)0, (int)(rowsA * Kp), kBufferFlags);
+  const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(qbT + (int64_t)n0 * Kp), (short)0, (int)(rowsB * Kp), kBufferFlags);
+  // DMA block d (1024 bytes) covers stage rows 16d .. 16d+15; block d of A is
+  // issued by wave d % NW as its (d / NW)-th A block.  The lane filling
+  // physical chunk p of row r fetches logical chunk p ^ swz4(r).
+  int voA[A_CH], voB[B_CH];
+#pragma unroll
+  for (int i = 0; i < A_CH; ++i) {
+    const int r = (i * NW + wave) * 16 + (lane >> 2);
+    voA[i] = r * (int)Kp + (((lane & 3) ^ swz4(r)) << 4);
+  }
+#pragma unroll
+  for (int i = 0; i < B_CH; ++i) {
+    const int r = (i * NW + wave) * 16 + (lane >> 2);
+    voB[i] = r * (int)Kp + (((lane & 3) ^ swz4(r)) << 4);
+  }
+  auto dma = [&](uint8_t *stage, int k0) {
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) lds_load16(rsA, stage + (i * NW + wave) * 1024, voA[i] + k0);
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i)
+      lds_load16(rsB, stage + BM * BK + (i * NW + wave) * 1024, voB[i] + k0);
+  };
+  const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+  const int lrow = lane & 31, lgrp = lane >> 5;
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+  auto mfma_slab = [&](const uint8_t *sA) {
+    const uint8_t *sB = sA + BM * BK;
+    const int c0 = lgrp * 2;  // the lane's 32 codes: logical chunks c0, c0 + 1
+    i32x8 a[FM], b[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int r = wm0 + i * 32 + lrow;
+      const uint4 lo = *reinterpret_cast<const uint4 *>(sA + r * BK + ((c0 ^ swz4(r)) << 4));
+      const uint4 hi = *reinterpret_cast<const uint4 *>(sA + r * BK + (((c0 + 1) ^ swz4(r)) << 4));
+      a[i] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int r = wn0 + j * 32 + lrow;
+      const uint4 lo = *reinterpret_cast<const uint4 *>(sB + r * BK + ((c0 ^ swz4(r)) << 4));
+      const uint4 hi = *reinterpret_cast<const uint4 *>(sB + r * BK + (((c0 + 1) ^ swz4(r)) << 4));
+      b[j] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                     0, 0, 0, 0);
+  };
+  // Kp is a multiple of 128, so KT >= 2.  DMAs past the last slab are clamped
+  // to it (in-bounds, never consumed): every iteration issues the same count,
+  // and the wait at its top leaves exactly the two later slabs in flight.
+  const int KT = (int)(Kp / BK);
+  auto kslab = [&](int sl) { return (sl < KT ? sl : KT - 1) * BK; };
+  constexpr int kPer = A_CH + B_CH;  // DMA instructions per wave and slab
+  // s_waitcnt with vmcnt = the two later slabs' DMAs (gfx9 encoding: vmcnt in
+  // bits 3:0 and 15:14), lgkmcnt = 0 (bits 11:8: this wave's LDS reads have
+  // completed, so no read of a stage is in flight when the barrier releases
+  // its refill), expcnt at its maximum (bits 6:4, no wait)
+  constexpr int kWaitTwoLater = ((2 * kPer) & 15) | (((2 * kPer) >> 4) << 14) | (7 << 4);
+  static_assert(2 * kPer < 64, "vmcnt range");
+  // step of slab t: cur = stage t % 4, prev = stage (t + 3) % 4, which held slab t-1
+  // The barrier is the bare instruction: a workgroup fence (as in
+  // __syncthreads) would wait for every outstanding load, the two later
+  // slabs' DMAs included.  The explicit wait before it covers slab t's DMA,
+  // the fragment reads of slab t-1 completed before the MFMAs that consumed
+  // them, and the empty asm statements keep the compiler from moving memory
+  // accesses across it.  The wait also drains this wave's LDS reads: the
+  // compiler may leave the last fragment reads of slab t-1 in flight across
+  // the barrier, and the DMA issued after it refills that stage.
+  auto step = [&](uint8_t *cur, uint8_t *prev, int t) {
+    __builtin_amdgcn_s_waitcnt(kWaitTwoLater);  // this wave's DMA of slab t has landed,
+                                                // its LDS reads are complete
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();  // ... and every wave's; every wave is done with slab t-1's stage
+    asm volatile("" ::: "memory");
+    dma(prev, kslab(t + 3));
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_slab(cur);
+  };
+  dma(st0, kslab(0));
+  dma(st1, kslab(1));
+  dma(st2, kslab(2));
+  int t = 0;
+  for (; t + 4 <= KT; t += 4) {
+    step(st0, st3, t);
+    step(st1, st0, t + 1);
+    step(st2, st1, t + 2);
+    step(st3, st2, t + 3);
+  }
+  if (t < KT) {  // KT is even: two slabs left
+    step(st0, st3, t);
+    step(st1, st0, t + 1);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the clamped DMAs have landed before the workgroup ends
+  epilogue<FM, FN, BM, BN, BETA>(acc, Mr, Nr, m0, n0, wm0, wn0, lrow, lgrp, alpha, sa, sb, beta,
+                                 C, ldc);
+}
+
 // Raw conversion, for verification of the encoder.
 __global__ __launch_bounds__(256) void encode_kernel(int64_t n, const float *__restrict__ x,
                                                      uint8_t *__restrict__ out) {
@@ -891,7 +1036,29 @@ static gemm_status fp8_launch(int64_t M, int64_t N, const fp8::Layout &L, float 
   return check_launch("gemm_fp8_kernel");
 }
 
-int fp8_num_configs() { return 6; }
+template <int BM, int BN, int WM, int WN>
+static gemm_status fp8_launch_ring(int64_t M, int64_t N, const fp8::Layout &L, float alpha,
+                                   const uint8_t *base, float beta, float *C, int64_t ldc,
+                                   hipStream_t s) {
+  if ((int64_t)(BM > BN ? BM : BN) * L.Kp >= ((int64_t)1 << 31)) {
+    set_error("gemm_fp8: K too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  const int tiles_m = (int)((M + BM - 1) / BM), tiles_n = (int)((N + BN - 1) / BN);
+  const dim3 grid((unsigned)((int64_t)tiles_m * tiles_n)), block(64 * (BM / WM) * (BN / WN));
+  const uint8_t *qa = base + L.qa, *qb = base + L.qb;
+  const float *sa = reinterpret_cast<const float *>(base + L.sa);
+  const float *sb = reinterpret_cast<const float *>(base + L.sb);
+  if (beta != 0.0f)
+    hipLaunchKernelGGL((fp8::gemm_fp8_ring_kernel<BM, BN, WM, WN, true>), grid, block, 0, s,
+                       (int)M, (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((fp8::gemm_fp8_ring_kernel<BM, BN, WM, WN, false>), grid, block, 0, s,
+                       (int)M, (int)N, L.Kp, alpha, qa, qb, sa, sb, beta, C, ldc, tiles_m, tiles_n);
+  return check_launch("gemm_fp8_ring_kernel");
+}
+
+int fp8_num_configs() { return 7; }
 const char *fp8_config_name(int cfg) {
   switch (cfg) {
     case 0: return "fp8_256x256x128_8w128x64";
@@ -899,6 +1066,7 @@ const char *fp8_config_name(int cfg) {
     case 3: return "fp8_128x128x128_4w64x64_dma";
     case 4: return "fp8_256x128x128_8w64x64_dma";
     case 5: return "fp8_256x256x128_4w128x128_dma";
+    case 6: return "fp8_256x256x64_8w128x64_dma_ring4";
     default: return "fp8_256x256x128_8w128x64_dma";
   }
 }
@@ -912,6 +1080,7 @@ gemm_status fp8_gemm_run_cfg(int64_t M, int64_t N, int64_t K, float alpha, const
   if (cfg == 3) return fp8_launch<128, 128, 64, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
   if (cfg == 4) return fp8_launch<256, 128, 64, 64, true>(M, N, L, alpha, base, beta, C, ldc, s);
   if (cfg == 5) return fp8_launch<256, 256, 128, 128, true>(M, N, L, alpha, base, beta, C, ldc, s);
+  if (cfg == 6) return fp8_launch_ring<256, 256, 128, 64>(M, N, L, alpha, base, beta, C, ldc, s);
   return fp8_launch<256, 256, 128, 64, false>(M, N, L, alpha, base, beta, C, ldc, s);
 }
 
