@@ -585,6 +585,10 @@ def main():
         one("fp8_prequantized_4096^3",
             lambda: mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.5, Cf, N),
             flops, PEAK_FP8_MFMA, "fp8_peak")
+        # beta = 0 (C write-only), the form a scaled-FP8 library GEMM computes
+        one("fp8_prequantized_4096^3_beta0",
+            lambda: mm.gemm_fp8_prequantized(M, N, K, 1.5, ws, nbytes, 0.0, Cf, N),
+            flops, PEAK_FP8_MFMA, "fp8_peak")
         del An, Bn, ws, Cf
         # binary64 on the FP64 matrix cores, and a batched-strided small-matrix
         # workload (2.0 GFLOP useful: 29 297 products of 32 x 32 x 32)
