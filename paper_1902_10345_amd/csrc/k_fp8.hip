@@ -370,6 +370,88 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int K, int N, int64_t
   }
 }
 
+// One-pass column quantisation for K <= 1024 * CQ: a workgroup of 1024 lanes
+// holds a stripe of 16 columns of the K x Nc matrix in registers between the
+// amax reduction and the encoding, so the matrix is read from HBM once (the
+// two-pass path reads it for the amax and again for the codes).  Lane (tx, ty)
+// = (tid & 3, tid >> 2) holds columns j0 + 4 tx .. + 3 of rows 4 (ty + 256 i)
+// .. + 3 (i < CQ): 4 consecutive k of each of its 4 columns, so each column's
+// codes come out as 32-bit words of 4 consecutive k, stored straight into the
+// transposed layout (row j of qT holds column j, k contiguous) -- the 16 lanes
+// of a wave with one tx write 64 contiguous bytes of each of their columns.
+// Stripes are remapped so that the two stripes of one 128-byte row segment
+// run on one XCD (their shared lines meet in its L2).  VEC: ld % 4 == 0 and
+// the base 16-byte aligned.
+template <int CQ, bool VEC>
+__global__ __launch_bounds__(1024) void quant_cols_reg_kernel(int K, int Nc, int64_t Kp,
+                                                              const float *__restrict__ B,
+                                                              int64_t ldb,
+                                                              uint8_t *__restrict__ qT,
+                                                              float *__restrict__ scales) {
+  __shared__ float red[16][16];
+  const int tid = threadIdx.x, tx = tid & 3, ty = tid >> 2;
+  const int stripe = xcd_remap(blockIdx.x, gridDim.x);
+  const int j0 = stripe * 16 + tx * 4;  // the lane's first column
+  float x[CQ][4][4];                    // [block i][row e][column c]
+  float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  bool nan[4] = {false, false, false, false};
+#pragma unroll
+  for (int i = 0; i < CQ; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * (ty + 256 * i) + e;
+      const float *p = B + (int64_t)k * ldb + j0;
+      if (VEC && k < K && j0 + 3 < Nc) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        x[i][e][0] = v.x; x[i][e][1] = v.y; x[i][e][2] = v.z; x[i][e][3] = v.w;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[i][e][c] = (k < K && j0 + c < Nc) ? p[c] : 0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        m[c] = fmaxf(m[c], fabsf(x[i][e][c]));
+        nan[c] |= x[i][e][c] != x[i][e][c];
+      }
+    }
+  // column maxima: over the 16 lanes of a wave with the same tx, then over
+  // the 16 waves
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) m[c] = fmaxf(m[c], __shfl_xor(m[c], o, 64));
+  const int wave = tid >> 6;
+  if ((tid & 63) < 4) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[wave][tx * 4 + c] = m[c];
+  }
+  __syncthreads();
+  float sc[4], rc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float a = red[0][tx * 4 + c];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) a = fmaxf(a, red[w][tx * 4 + c]);
+    sc[c] = (a == 0.0f) ? 1.0f : a / 448.0f;
+    rc[c] = 1.0f / sc[c];
+    if (ty == 0 && j0 + c < Nc) scales[j0 + c] = sc[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (j0 + c >= Nc) continue;
+    uint8_t *q = qT + (int64_t)(j0 + c) * Kp;
+    auto emit = [&](auto mode) {
+#pragma unroll
+      for (int i = 0; i < CQ; ++i) {
+        const int k = 4 * (ty + 256 * i);
+        const float g[4] = {x[i][0][c], x[i][1][c], x[i][2][c], x[i][3][c]};
+        if (k < Kp) *reinterpret_cast<uint32_t *>(q + k) = codes4<decltype(mode)::value>(g, sc[c], rc[c]);
+      }
+    };
+    with_mode(sc[c], nan[c], emit);  // per column: lanes may take different modes
+  }
+}
+
 // ---------------------------------------------------------------- GEMM ----
 // 256 x 256 tile, 128-byte K slabs, 2 x 2 waves of 128 x 128, MFMA
 // v_mfma_f32_32x32x64_f8f6f4 with both operands E4M3.  LDS rows are 128
@@ -959,6 +1041,26 @@ static gemm_status quant_rows(int64_t R, int64_t K, int64_t Kp, const float *P, 
 static gemm_status quant_cols(int64_t K, int64_t Nc, int64_t Kp, const float *P, int64_t ld,
                               uint32_t *amax, uint8_t *q, float *scales, hipStream_t s,
                               bool amax_clear = false) {
+  // up to 4096 rows: one pass, the stripe held in registers
+  if (Kp <= 4096) {
+    const bool vec1 = ld % 4 == 0 && ((uintptr_t)P & 15) == 0;
+    const dim3 grid((unsigned)((Nc + 15) / 16));
+#define MM_QCOLS(CQ)                                                                             \
+  do {                                                                                           \
+    if (vec1)                                                                                    \
+      hipLaunchKernelGGL((fp8::quant_cols_reg_kernel<CQ, true>), grid, dim3(1024), 0, s, (int)K, \
+                         (int)Nc, Kp, P, ld, q, scales);                                         \
+    else                                                                                         \
+      hipLaunchKernelGGL((fp8::quant_cols_reg_kernel<CQ, false>), grid, dim3(1024), 0, s,        \
+                         (int)K, (int)Nc, Kp, P, ld, q, scales);                                 \
+  } while (0)
+    if (Kp <= 1024) MM_QCOLS(1);
+    else if (Kp <= 2048) MM_QCOLS(2);
+    else if (Kp <= 3072) MM_QCOLS(3);
+    else MM_QCOLS(4);
+#undef MM_QCOLS
+    return check_launch("quant_cols_reg_kernel");
+  }
   if (!amax_clear) {
     const unsigned fg = (unsigned)std::min<int64_t>((Nc + 255) / 256, 1024);
     hipLaunchKernelGGL(fp8::fill_u32_kernel, dim3(fg), dim3(256), 0, s, amax, Nc);

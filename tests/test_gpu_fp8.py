@@ -78,6 +78,23 @@ def test_quantiser_is_bitwise_the_oracle(M, N, K, outliers):
     assert not qa[:, K:].any() and not qbT[:, K:].any()
 
 
+@pytest.mark.parametrize("K", [1024, 1025, 2048, 3072, 3073, 4096, 4100])
+def test_column_quantiser_register_blocks_are_bitwise_the_oracle(K):
+    """The one-pass column quantiser (a stripe of 16 columns held in
+    registers, up to 4096 padded rows in blocks of 1024) at the edges of its
+    row blocks, a partial last stripe (N = 37) and columns of A-transposed
+    shape; K = 4100 takes the two-pass path."""
+    import paper_1902_10345_amd as mm
+    M, N = 5, 37
+    A, B, _ = si.fp8_workload(M, N, K, seed=K, outliers="B")
+    B[K - 1, 36] = np.float32(-3.5e3)  # the last row of the last column sets its scale
+    _, _, qa, qbT, sa, sb, Kp = _quantize(mm, A, B)
+    rsb = oracle.fp8_scales_cols(B)
+    assert np.array_equal(sb, rsb)
+    assert np.array_equal(qbT[:, :K].T, oracle.fp8_quantize_cols(B, rsb))
+    assert not qbT[:, K:].any()
+
+
 @pytest.mark.parametrize("M,N,K", [(40, 36, 200), (40, 36, 1000), (12, 20, 9000)])
 def test_quantiser_special_values_are_bitwise_the_oracle(M, N, K):
     """Rows and columns with NaN, infinities, signed zeros and scales of
