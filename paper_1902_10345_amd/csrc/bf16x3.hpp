@@ -137,12 +137,13 @@ struct Stage {
   const float *P;
   int64_t ld;
   int r0, nrows, K;
+  int tl;  // the lane's index among the threads that share this staging
 
   // P: the operand as stored; ld: its row stride; r0: the tile's first LDS
   // row (output row of A / column of B); total: rows (KC) or row-index extent.
   __device__ __forceinline__ void init(const float *P_, int64_t ld_, int r0_, int total, int K_,
                                        int tid) {
-    P = P_; ld = ld_; r0 = r0_; K = K_;
+    P = P_; ld = ld_; r0 = r0_; K = K_; tl = tid;
     nrows = total - r0 < ROWS ? total - r0 : ROWS;
     if constexpr (KC) {
       // valid bytes end with the last valid row's K elements: reads past the
@@ -226,7 +227,7 @@ struct Stage {
       } else {  // partial slab: per-element offsets, invalid ones pushed out of range
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-          const int k = k0 + chunk_of((int)threadIdx.x + NT * i) * 8;
+          const int k = k0 + chunk_of(tl + NT * i) * 8;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int off = (k + e >= 0 && k + e < K) ? voff[i] + (k0 + e) * 4 : (int)0x80000000;
@@ -250,7 +251,7 @@ struct Stage {
       } else {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-          const int idx = (int)threadIdx.x + NT * i;
+          const int idx = tl + NT * i;
           const int n = row_of(idx);
           const int c = __builtin_amdgcn_readfirstlane(chunk_of(idx));  // wave-uniform
 #pragma unroll
@@ -280,7 +281,7 @@ struct Stage {
 // unpredicated load path; edge slabs take a guarded path that reads zeros
 // outside the matrices.  The choice is uniform across the workgroup.
 template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA,
-          bool TA = false, bool TB = false, int ST = 2, int SETS_ = 0>
+          bool TA = false, bool TB = false, int ST = 2, int SETS_ = 0, int KG = 1>
 __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
                                      const float *__restrict__ A, int64_t lda,
                                      const float *__restrict__ B, int64_t ldb, float beta,
@@ -290,7 +291,20 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
   static_assert(ST == 2 || (ST == 3 && NP == 2 && BK == 16),
                 "the three-stage ring is built for 16-deep slabs of three products");
   constexpr int NT = G::NT;
-  const int tid = threadIdx.x;
+  // KG > 1: the workgroup holds KG groups of NW waves; group g multiplies the
+  // g-th of KG equal k ranges (the caller guarantees K % KG == 0) into the
+  // same output tile with its own LDS stages (lds + g * LDS_BYTES), and the
+  // partial tiles are summed in group order before the epilogue.
+  static_assert(KG == 1 || (KG == 2 && !TA && !TB && ST == 2),
+                "k-groups: two groups, operands not transposed, two LDS stages");
+  const int grp = KG > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT) : 0;
+  const int tid = (int)threadIdx.x - grp * NT;
+  if constexpr (KG > 1) {
+    K /= KG;
+    A += (int64_t)grp * K;
+    B += (int64_t)grp * K * ldb;
+    lds += grp * (G::LDS_BYTES / 2);
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int Mr = M - m0, Nr = N - n0;
   const bool interior = Mr >= BM && Nr >= BN;
@@ -850,6 +864,34 @@ __device__ __forceinline__ void tile(int M, int N, int K, float alpha,
     if (t < KT) {  // odd slab count: the last slab sits in stage 0
       mfma_stage(0);
     }
+  }
+
+  // ---- sum of the k-groups' partial tiles (group order) --------------------
+  if constexpr (KG > 1) {
+    // every fragment read of both groups is done before their stages are
+    // reused; group 1 leaves its partial tile in LDS lane-contiguous (the
+    // two groups' stages together hold exactly one group's accumulators)
+    float *red = reinterpret_cast<float *>(lds - grp * (G::LDS_BYTES / 2));
+    static_assert(G::NT * G::FM * G::FN * 16 * 4 <= KG * G::LDS_BYTES, "partial tile fits");
+    __syncthreads();
+    if (grp == 1) {
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+          for (int e = 0; e < 16; ++e)
+            red[(((wave * G::FM + i) * G::FN + j) * 16 + e) * 64 + lane] = acc[i][j][e];
+    }
+    __syncthreads();
+    if (grp == 1) return;
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          acc[i][j][e] += red[(((wave * G::FM + i) * G::FN + j) * 16 + e) * 64 + lane];
   }
 
   // ---- peeled epilogue ----------------------------------------------------

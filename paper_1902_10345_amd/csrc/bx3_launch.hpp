@@ -23,6 +23,23 @@ __global__ __launch_bounds__(64 * NW, 1) void gemm_bx3_kernel(
                                                           C, ldc, tm * BM, tn * BN, lds);
 }
 
+// The tile with its k range split between two groups of NW waves (one
+// workgroup of 2 * NW waves per tile): twice the waves per SIMD of the
+// one-group tile where its tiles come to about one per CU.
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW, bool VEC, bool BETA>
+__global__ __launch_bounds__(128 * NW, 1) void gemm_bx3_kg_kernel(
+    int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda,
+    const float *__restrict__ B, int64_t ldb, float beta, float *__restrict__ C, int64_t ldc,
+    int tiles_m, int tiles_n) {
+  using G = Cfg<BM, BN, BK, WM, WN, NP, NW>;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * G::LDS_BYTES / 2];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  tile_coords(wg, tiles_m, tiles_n, 8, tm, tn);
+  tile<BM, BN, BK, WM, WN, NP, NW, VEC, BETA, false, false, 2, 0, 2>(
+      M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, tm * BM, tn * BN, lds);
+}
+
 // The plain binary32 product on the FP32 matrix cores (v_mfma_f32_32x32x2f32):
 // the same tile body in its FP32 mode (no split; binary32 in LDS).
 template <int BM, int BN, int BK, int WM, int WN, int NW, bool VEC, bool BETA, bool TA, bool TB>
@@ -169,6 +186,36 @@ gemm_status launch_batched(const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc
 // The tile configurations that have transposed-operand variants (the ones the
 // library picks by default): 0, 2, 3, 4, 5, 6 and 8 of the split path, both
 // FP32 matrix-core tiles.
+// Two k-groups per workgroup; K odd has no equal halves (UNSUPPORTED: the
+// configuration choice sends such shapes elsewhere).
+template <int BM, int BN, int BK, int WM, int WN, int NP, int NW>
+gemm_status launch_kg(const GemmArgs &g, hipStream_t s) {
+  if (g.K % 2 != 0) {
+    set_error("gemm_f32_3xbf16: the two-group configuration needs an even K");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  const int tiles_m = (int)((g.M + BM - 1) / BM);
+  const int tiles_n = (int)((g.N + BN - 1) / BN);
+  const int64_t nwg = (int64_t)tiles_m * tiles_n;
+  if (nwg > 0x7fffffff) { set_error("gemm_f32_3xbf16: too many tiles"); return GEMM_STATUS_UNSUPPORTED; }
+  if (!offsets_fit<BM, BN, BK, false, false>(g)) {
+    set_error("gemm_f32_3xbf16: lda or ldb too large for 32-bit tile offsets");
+    return GEMM_STATUS_UNSUPPORTED;
+  }
+  // each group's panel starts K/2 elements into a row of A
+  const bool vec = vector_loads_ok<false, false>(g) && (g.K / 2) % 4 == 0;
+  const bool beta = g.beta != 0.0f;
+  dim3 grid((unsigned)nwg), block(128 * NW);
+#define MM_LAUNCH(V, BT)                                                                   \
+  hipLaunchKernelGGL((gemm_bx3_kg_kernel<BM, BN, BK, WM, WN, NP, NW, V, BT>), grid, block, \
+                     0, s, (int)g.M, (int)g.N, (int)g.K, g.alpha, g.A, g.lda, g.B, g.ldb,  \
+                     g.beta, g.C, g.ldc, tiles_m, tiles_n)
+  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
+  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
+#undef MM_LAUNCH
+  return check_launch("gemm_bx3_kg_kernel");
+}
+
 template <bool TA, bool TB>
 gemm_status bx3_run_trans(const GemmArgs &g, int cfg, hipStream_t s) {
   switch (cfg) {

@@ -162,6 +162,9 @@ static const Bx3Config kBx3Configs[] = {
     // the 256 x 256 x 16 tile with a ring of three LDS stages: the first
     // product's fragments of the next slab are read before the barrier
     {{256, 256, 16, "bx3_256x256x16_8w128x64_p3_ring3"}, 2},
+    // 128 x 128 x 16 tiles, the k range split between two groups of four
+    // waves (partial tiles summed through LDS in group order)
+    {{128, 128, 16, "bx3_128x128x16_2x4w64x64_p3_kg2"}, 2},
 };
 
 int bx3_num_configs() { return (int)(sizeof(kBx3Configs) / sizeof(kBx3Configs[0])); }
@@ -172,7 +175,6 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   const int64_t cus = num_cus();
   auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
   const int64_t big = tiles(256, 256);
-  (void)K;
   // Shapes whose 128 x 128 tiles leave CUs idle: the small-product tiles (the
   // k range split over a workgroup's eight waves), measured by graph replay
   // over 19 shapes: 32 x 32 tiles up to two per CU (256^3: 3.7 us against
@@ -200,7 +202,14 @@ int bx3_default_config(int64_t M, int64_t N, int64_t K, int n_products) {
   // by 4 % with beta != 0); the small-product tiles below that.
   const int64_t mid = tiles(256, 128);
   if (mid * 4 >= cus * 3 && mid <= cus) return 2;
-  if (tiles(128, 128) >= cus) return 8;
+  // 128 x 128 tiles for more than half of the CUs and at most all of them:
+  // the tile with its k range split between two groups of four waves (two
+  // waves per SIMD instead of one), measured over eight shapes: 2048^3 64.9
+  // -> 57.6 us, 1792^3 62.2 -> 44.5 (the 64 x 64 tile before), 1536^3 42.0 ->
+  // 37.6; at half of the CUs and below the 64 x 64 tiles stay ahead
+  const int64_t t128 = tiles(128, 128);
+  if (t128 <= cus && 2 * t128 > cus && K % 2 == 0) return 14;
+  if (t128 >= cus) return 8;
   return small(9, 10, 6);
 }
 
@@ -218,6 +227,7 @@ gemm_status bx3_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 7: return bx3::launch<256, 256, 16, 128, 128, 2, 4>(g, s);
     case 8: return bx3::launch<128, 128, 16, 64, 64, 2, 4>(g, s);
     case 13: return bx3::launch<256, 256, 16, 128, 64, 2, 8, false, false, 3>(g, s);
+    case 14: return bx3::launch_kg<128, 128, 16, 64, 64, 2, 4>(g, s);
     default: set_error("gemm_f32_3xbf16: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }
@@ -245,6 +255,13 @@ gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *
 }
 
 gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
+  if (which == 2) {
+    if (g.ta || g.tb) {
+      set_error("gemm_ex: the two-group FP32 matrix-core tile takes no transposed operands");
+      return GEMM_STATUS_UNSUPPORTED;
+    }
+    return bx3::launch_kg<128, 128, 16, 64, 64, 1, 4>(g, s);
+  }
   if (g.ta || g.tb)
     return g.ta ? (g.tb ? f32mfma_run_tt(g, which, s) : f32mfma_run_tn(g, which, s))
                 : f32mfma_run_nt(g, which, s);

@@ -260,13 +260,15 @@ static const TileConfig kF32Configs[] = {
     // over the waves (binary32 matrix cores, ordered sum through LDS)
     {32, 32, 8, "f32_small_32x32_8wk"},
     {64, 64, 8, "f32_small_64x64_8wk"},
+    // the FP32 matrix-core 128 x 128 tile with its k range split between two
+    // groups of four waves (partial tiles summed through LDS in group order)
+    {128, 128, 16, "f32mfma_128x128x16_2x4w64x64_kg2"},
 };
 
 int f32_num_configs() { return (int)(sizeof(kF32Configs) / sizeof(kF32Configs[0])); }
 const TileConfig &f32_config(int i) { return kF32Configs[i]; }
 
 int f32_default_config(int64_t M, int64_t N, int64_t K) {
-  (void)K;
   // measured: the FP32 matrix-core tiles win while they fill every CU (256 x
   // 256: 140 TFLOP/s at 4096^3 against 90 on the vector ALU).  Below that the
   // small-product tiles (the k range split over a workgroup's eight waves)
@@ -276,7 +278,13 @@ int f32_default_config(int64_t M, int64_t N, int64_t K) {
   const int64_t cus = num_cus();
   auto tiles = [&](int64_t b) { return ((M + b - 1) / b) * ((N + b - 1) / b); };
   if (tiles(256) >= cus) return 5;
-  if (tiles(128) >= cus) return 6;
+  // 128 x 128 tiles for more than three quarters of the CUs and at most all
+  // of them: the matrix-core tile with its k range split between two groups
+  // of four waves (2048^3 166.8 -> 151.6 us, 1792^3 126.6 against 147.9 for
+  // the small-product tiles); fewer tiles: the small-product tiles
+  const int64_t t128 = tiles(128);
+  if (t128 <= cus && 4 * t128 > 3 * cus && K % 2 == 0) return 9;
+  if (t128 >= cus) return 6;
   return tiles(64) >= cus ? 8 : 7;
 }
 
@@ -295,6 +303,7 @@ gemm_status f32_run(const GemmArgs &g, int cfg, hipStream_t s) {
     case 6: return f32mfma_run(g, 1, s);
     case 7: return small_run(g, 0, 1, s);
     case 8: return small_run(g, 1, 1, s);
+    case 9: return f32mfma_run(g, 2, s);
     default: set_error("gemm_f32: bad tile config"); return GEMM_STATUS_UNSUPPORTED;
   }
 }

@@ -106,6 +106,22 @@ def test_ring_config_every_slab_count_parity(K):
     _check(A, B, C0, C, 1.5, 0.5, 3)
 
 
+@pytest.mark.parametrize("K", [2, 16, 34, 130, 1000, 2048])
+def test_two_group_config_parity(K):
+    """The 128 x 128 tile with its k range split between two groups of four
+    waves: partial first slabs in each half, ragged M and N; an odd K is
+    refused (no equal halves)."""
+    import paper_1902_10345_amd as mm
+    cfg = [c for c in range(mm.gemm_num_configs(mm.PATH_3XBF16))
+           if mm.gemm_config_name(mm.PATH_3XBF16, c) == "bx3_128x128x16_2x4w64x64_p3_kg2"][0]
+    M, N = 300, 260
+    A, B, C0, _, C = _run(mm, M, N, K, 1.5, 0.5, 3, seed=K + 9, cfg=cfg)
+    _check(A, B, C0, C, 1.5, 0.5, 3)
+    with pytest.raises(mm.GemmError) as e:
+        _run(mm, M, N, 7, 1.5, 0.5, 3, seed=1, cfg=cfg)
+    assert e.value.status == mm.STATUS_UNSUPPORTED
+
+
 def test_mismatched_products_for_config_is_rejected():
     import paper_1902_10345_amd as mm
     cfg6 = [c for c in range(mm.gemm_num_configs(mm.PATH_3XBF16))

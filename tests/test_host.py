@@ -348,7 +348,12 @@ def test_default_tile_rules_for_underfilled_shapes():
     assert name(mm.PATH_F32, 1024, 1024, 1024) == "f32_small_64x64_8wk"
     assert name(mm.PATH_3XBF16, 1024, 1024, 1024) == "bx3_small_64x64_8wk_p3"
     assert name(mm.PATH_3XBF16, 64, 4096, 4096) == "bx3_small_32x32_8wk_p3"
-    assert name(mm.PATH_3XBF16, 1536, 1536, 512) == "bx3_64x64x32_4w32x32_p3"
-    assert name(mm.PATH_F32, 2048, 2048, 2048) == "f32mfma_128x128x16_4w64x64"
+    assert name(mm.PATH_3XBF16, 1536, 1536, 512) == "bx3_128x128x16_2x4w64x64_p3_kg2"
+    assert name(mm.PATH_3XBF16, 2048, 2048, 2048) == "bx3_128x128x16_2x4w64x64_p3_kg2"
+    assert name(mm.PATH_3XBF16, 2048, 2048, 2047) == "bx3_128x128x16_4w64x64_p3"  # odd K
+    assert name(mm.PATH_3XBF16, 2048, 1024, 4096) == "bx3_64x64x32_4w32x32_p3"
+    assert name(mm.PATH_F32, 2048, 2048, 2048) == "f32mfma_128x128x16_2x4w64x64_kg2"
+    assert name(mm.PATH_F32, 2048, 1536, 2048) == "f32_small_64x64_8wk"
+    assert name(mm.PATH_F32, 2560, 2048, 2048) == "f32mfma_128x128x16_4w64x64"
     assert name(mm.PATH_F32, 4096, 4096, 4096) == "f32mfma_256x256x16_8w128x64"
     assert name(mm.PATH_3XBF16, 4096, 4096, 4096) == "bx3_256x256x16_8w128x64_p3"
