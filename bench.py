@@ -616,6 +616,11 @@ def main():
                                                  ms_, sz, 0.0, Cb, ms_, sz, nb_, 3),
             2.0 * ms_ ** 3 * nb_, PEAK_BF16_MFMA, "bf16_peak")
         paths[key]["hbm_gbs"] = round(3 * 4 * sz * nb_ / (paths[key]["ms"] * 1e-3) / 1e9, 1)
+        key = "f32_sbsmm_32x32x32_x%d" % nb_
+        one(key, lambda: mm.gemm_strided_batched(mm.PATH_F32, ms_, ms_, ms_, 1.0, Ab, ms_, sz, Bb,
+                                                 ms_, sz, 0.0, Cb, ms_, sz, nb_, 3),
+            2.0 * ms_ ** 3 * nb_, PEAK_FP32_VALU, "fp32_peak")
+        paths[key]["hbm_gbs"] = round(3 * 4 * sz * nb_ / (paths[key]["ms"] * 1e-3) / 1e9, 1)
         del Ab, Bb, Cb
         M2, N2, K2 = 8192, 2048, 4096
         _, (A2, B2, C2) = _dev_inputs(M2, N2, K2, 3, torch)

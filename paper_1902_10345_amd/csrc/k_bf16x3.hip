@@ -132,6 +132,245 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, const float *__re
   }
 }
 
+// ---- batched small problems --------------------------------------------------
+// M, N <= 32 SB: one wave per problem, four problems per workgroup.  The
+// operands go from memory straight into MFMA fragments (and are split in
+// registers, NP = 2 or 3 planes; NP = 1 is binary32 on the FP32 matrix
+// cores): every element is used by one wave only, so staging through LDS
+// would add traffic and barriers, and the 64 x 64 tile of four waves would
+// leave three of them on padding for a 32 x 32 problem.  A lane holds 8
+// consecutive k of its A row (two 128-bit loads) and of its B column (eight
+// loads, consecutive lanes on consecutive columns) per 16-deep k-step.  The
+// k-steps lie on the grid that ends at K (only the first can be partial) and
+// the products come in the tile kernels' order, so every element is the same
+// sum as in the LDS-staged tiles of the same product count.
+template <int SB, int NP, bool VEC, bool BETA>
+__global__ __launch_bounds__(256) void small_batched_bx3_kernel(
+    int M, int N, int K, float alpha, const float *__restrict__ A, int64_t lda, int64_t sa,
+    const float *__restrict__ B, int64_t ldb, int64_t sb, float beta, float *__restrict__ C,
+    int64_t ldc, int64_t sc, int batch) {
+  const int lane = threadIdx.x & 63;
+  // the wave index is uniform across the wave; saying so keeps the problem's
+  // buffer resources in scalar registers
+  const int prob = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (prob >= batch) return;
+  const int lr = lane & 31, lg = lane >> 5;
+  // rows past M and columns past N read zero through the range check (their
+  // results are never stored); k below 0 is masked per element
+  const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(A + (int64_t)prob * sa), (short)0,
+      (int)(((int64_t)(M - 1) * lda + K) * 4), kBufferFlags);
+  const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(B + (int64_t)prob * sb), (short)0,
+      (int)(((int64_t)(K - 1) * ldb + N) * 4), kBufferFlags);
+  const __amdgpu_buffer_rsrc_t rC = __builtin_amdgcn_make_buffer_rsrc(
+      C + (int64_t)prob * sc, (short)0, (int)(((int64_t)(M - 1) * ldc + N) * 4), kBufferFlags);
+  int arow[SB], bcol[SB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    const int r = 32 * i + lr;
+    arow[i] = r < M ? r * (int)lda * 4 : (int)0x80000000;
+  }
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    const int n = 32 * j + lr;
+    bcol[j] = n < N ? n * 4 : (int)0x80000000;
+  }
+  const int ldb4 = (int)ldb * 4;
+  f32x16 acc[SB][SB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+  auto ld = [](__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  };
+  // the 8 values of one block as NP bf16 planes (plane 0 the leading part)
+  constexpr int NPL = NP > 1 ? NP : 2;
+  auto split8 = [](const float (&x)[8], bf16x8 (&pl)[NPL]) {
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      bf16x2 x0, x1, x2;
+      if constexpr (NP == 2) split2(f32x2{x[e], x[e + 1]}, x0, x1);
+      else split3(f32x2{x[e], x[e + 1]}, x0, x1, x2);
+      pl[0][e] = x0.x; pl[0][e + 1] = x0.y;
+      pl[1][e] = x1.x; pl[1][e + 1] = x1.y;
+      if constexpr (NP == 3) { pl[2][e] = x2.x; pl[2][e + 1] = x2.y; }
+    }
+  };
+  const int KT = (K + 15) / 16;
+  const int kbase = K - KT * 16;
+  for (int s = 0; s < KT; ++s) {
+    if constexpr (NP == 1) {
+      // binary32 on v_mfma_f32_32x32x2f32, as in the FP32 tile: lane group g
+      // holds k = 4g + q and 8 + 4g + q (q < 4) of the step, and MFMA
+      // 4h + q takes element 4h + q of both groups
+      const int kb = kbase + 16 * s + 4 * lg;
+      float a[SB][8], b[SB][8];
+      if (s > 0 || kbase == 0) {
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+          if (VEC) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                            rA, arow[i] + (kb + 8 * h) * 4, 0, 0));
+              a[i][4 * h] = v.x; a[i][4 * h + 1] = v.y;
+              a[i][4 * h + 2] = v.z; a[i][4 * h + 3] = v.w;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              a[i][e] = ld(rA, arow[i] + (kb + 8 * (e >> 2) + (e & 3)) * 4);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            b[j][e] = ld(rB, bcol[j] + (kb + 8 * (e >> 2) + (e & 3)) * ldb4);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = kb + 8 * (e >> 2) + (e & 3);
+#pragma unroll
+          for (int i = 0; i < SB; ++i)
+            a[i][e] = ld(rA, k >= 0 ? arow[i] + k * 4 : (int)0x80000000);
+#pragma unroll
+          for (int j = 0; j < SB; ++j)
+            b[j][e] = ld(rB, k >= 0 ? bcol[j] + k * ldb4 : (int)0x80000000);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+#pragma unroll
+          for (int j = 0; j < SB; ++j)
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], b[j][e], acc[i][j], 0, 0, 0);
+      continue;
+    }
+    const int k0 = kbase + 16 * s + 8 * lg;  // the lane's first k of this step
+    float a[SB][8], b[SB][8];
+    if (s > 0 || kbase == 0) {
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        if (VEC) {
+          const f32x4 v0 = __builtin_bit_cast(
+              f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, arow[i] + k0 * 4, 0, 0));
+          const f32x4 v1 = __builtin_bit_cast(
+              f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, arow[i] + k0 * 4 + 16, 0, 0));
+          a[i][0] = v0.x; a[i][1] = v0.y; a[i][2] = v0.z; a[i][3] = v0.w;
+          a[i][4] = v1.x; a[i][5] = v1.y; a[i][6] = v1.z; a[i][7] = v1.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a[i][e] = ld(rA, arow[i] + (k0 + e) * 4);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < SB; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[j][e] = ld(rB, bcol[j] + (k0 + e) * ldb4);
+    } else {
+      // the partial first step: k in [kbase, kbase + 16) with kbase < 0
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool kin = k0 + e >= 0;
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+          a[i][e] = ld(rA, kin ? arow[i] + (k0 + e) * 4 : (int)0x80000000);
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+          b[j][e] = ld(rB, kin ? bcol[j] + (k0 + e) * ldb4 : (int)0x80000000);
+      }
+    }
+    bf16x8 pa[SB][NPL], pb[SB][NPL];
+#pragma unroll
+    for (int i = 0; i < SB; ++i) split8(a[i], pa[i]);
+#pragma unroll
+    for (int j = 0; j < SB; ++j) split8(b[j], pb[j]);
+    auto prod = [&](int qa, int qb) {
+#pragma unroll
+      for (int i = 0; i < SB; ++i)
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pa[i][qa], pb[j][qb], acc[i][j],
+                                                              0, 0, 0);
+    };
+    // small products first, the leading product last
+    if constexpr (NP == 3) {
+      prod(2, 0);
+      prod(1, 1);
+      prod(0, 2);
+    }
+    prod(1, 0);
+    prod(0, 1);
+    prod(0, 0);
+  }
+  // 32 x 32 block layout: lane l, element e -> row 8*(e/4) + 4*(l/32) + e%4,
+  // column l%32.  Columns past N get an out-of-range offset; rows past M fall
+  // beyond the resource and their stores are dropped.  With beta != 0 every
+  // read of C is issued before the first store.
+  const int ldc4 = (int)ldc * 4;
+  int vb[SB][SB];
+  float cold[SB][SB][16];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      const int col = 32 * j + lr;
+      vb[i][j] = col < N ? (32 * i + 4 * lg) * ldc4 + col * 4 : (int)0x80000000;
+      if (BETA) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          cold[i][j][e] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(rC, vb[i][j],
+                                                          (8 * (e >> 2) + (e & 3)) * ldc4, 0));
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        float v = alpha * acc[i][j][e];
+        if (BETA) v = fmaf(beta, cold[i][j][e], v);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rC, vb[i][j],
+                                              (8 * (e >> 2) + (e & 3)) * ldc4, 0);
+      }
+}
+
+// Offsets of the small-problem kernel stay below 2^31: 64 rows of A and of C,
+// K rows of B.
+bool small_batched_fits(const GemmArgs &g) {
+  const int64_t lim = (int64_t)1 << 31;
+  return ((int64_t)64 * g.lda + g.K) * 4 < lim && ((int64_t)g.K * g.ldb + g.N) * 4 < lim &&
+         ((int64_t)64 * g.ldc + g.N) * 4 < lim;
+}
+
+// At most 65535 problems per launch (the caller's chunks).
+template <int SB, int NP>
+gemm_status launch_small_batched(const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,
+                                 int batch, hipStream_t s) {
+  // 128-bit A loads: 16-byte aligned rows and k offsets (K % 4 == 0 keeps the
+  // step grid on multiples of 4)
+  const bool vec = g.lda % 4 == 0 && g.K % 4 == 0 && sa % 4 == 0 && ((uintptr_t)g.A & 15) == 0;
+  const bool beta = g.beta != 0.0f;
+  const dim3 grid((unsigned)((batch + 3) / 4)), block(256);
+#define MM_LAUNCH(V, BT)                                                                         \
+  hipLaunchKernelGGL((small_batched_bx3_kernel<SB, NP, V, BT>), grid, block, 0, s, (int)g.M,      \
+                     (int)g.N, (int)g.K, g.alpha, g.A, g.lda, sa, g.B, g.ldb, sb, g.beta, g.C,     \
+                     g.ldc, sc, batch)
+  if (vec) { if (beta) MM_LAUNCH(true, true); else MM_LAUNCH(true, false); }
+  else     { if (beta) MM_LAUNCH(false, true); else MM_LAUNCH(false, false); }
+#undef MM_LAUNCH
+  return check_launch("small_batched_bx3_kernel");
+}
+
 }  // namespace bx3
 
 constexpr int kSplitKMax = 64;
@@ -269,17 +508,24 @@ gemm_status f32mfma_run(const GemmArgs &g, int which, hipStream_t s) {
   return bx3::launch_f32mfma<128, 128, 16, 64, 64, 4>(g, s);
 }
 
-// Batched-strided products on the matrix-core tiles.  The tile follows the
-// problem's size and the batch's total tile count: 64 x 64 tiles for small
-// problems (128 x 128 for six products and for binary32), otherwise the
-// single-GEMM choice for a problem stacked batch times along M.
+// Batched-strided products.  Small problems, one wave per problem
+// (small_batched_bx3_kernel): binary32 and six products for M, N <= 64, three
+// products while M N <= 48^2 (beyond that the 64 x 64 tile of four waves is
+// faster: 64^3 x 8000 71 against 78 us).  Otherwise the tile follows the
+// problem's size and the batch's total tile count: the single-GEMM choice for
+// a problem stacked batch times along M (binary32: 256 x 256 or 128 x 128
+// tiles on the FP32 matrix cores).
 int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, int64_t batch) {
   if (path == GEMM_PATH_F32) {
+    if (M <= 64 && N <= 64) return kBatchedSmall1;
     const int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
     if (tiles <= 0) return 1;
     return batch >= (num_cus() + tiles - 1) / tiles ? 0 : 1;  // f32mfma 256 x 256 / 128 x 128
   }
-  if (M <= 64 && N <= 64) return n_products == 6 ? 5 : 6;
+  if (M <= 64 && N <= 64) {
+    if (n_products == 6) return kBatchedSmall6;
+    return M * N <= 48 * 48 ? kBatchedSmall3 : 6;
+  }
   // M stacked batch times (saturated: only the tile count's size matters)
   const int64_t stacked = M <= 0 ? 0 : batch > ((int64_t)1 << 40) / M ? ((int64_t)1 << 40) : M * batch;
   const int cfg = bx3_default_config(stacked, N, K, n_products);
@@ -291,9 +537,25 @@ int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, in
 
 gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,
                         int batch, hipStream_t s) {
-  if (path == GEMM_PATH_F32)
+  if (path == GEMM_PATH_F32) {
+    if (cfg == kBatchedSmall1 && bx3::small_batched_fits(g))
+      return g.M <= 32 && g.N <= 32 ? bx3::launch_small_batched<1, 1>(g, sa, sb, sc, batch, s)
+                                    : bx3::launch_small_batched<2, 1>(g, sa, sb, sc, batch, s);
     return cfg == 0 ? bx3::launch_batched<256, 256, 16, 128, 64, 1, 8>(g, sa, sb, sc, batch, s)
                     : bx3::launch_batched<128, 128, 16, 64, 64, 1, 4>(g, sa, sb, sc, batch, s);
+  }
+  if (cfg == kBatchedSmall3 || cfg == kBatchedSmall6) {
+    // one wave per problem; offsets beyond 32 bits take the LDS-staged tile
+    // of the same product count (the same per-element sums)
+    const bool six = cfg == kBatchedSmall6, one = g.M <= 32 && g.N <= 32;
+    if (bx3::small_batched_fits(g)) {
+      if (six) return one ? bx3::launch_small_batched<1, 3>(g, sa, sb, sc, batch, s)
+                          : bx3::launch_small_batched<2, 3>(g, sa, sb, sc, batch, s);
+      return one ? bx3::launch_small_batched<1, 2>(g, sa, sb, sc, batch, s)
+                 : bx3::launch_small_batched<2, 2>(g, sa, sb, sc, batch, s);
+    }
+    cfg = six ? 5 : 6;
+  }
   switch (cfg) {
     case 0: return bx3::launch_batched<256, 256, 16, 128, 64, 2, 8>(g, sa, sb, sc, batch, s);
     case 2: return bx3::launch_batched<256, 128, 32, 64, 64, 2, 8>(g, sa, sb, sc, batch, s);

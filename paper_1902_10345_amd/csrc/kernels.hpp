@@ -54,6 +54,9 @@ gemm_status bx3_run_splitk(const GemmArgs &g, int n_products, int splits, void *
 // binary32 matrix cores, 2 / 3 = bf16 planes per operand (3 / 6 products).
 gemm_status small_run(const GemmArgs &g, int which, int np, hipStream_t s);
 // Batched-strided products (binary32 or split precision) on the MFMA tiles.
+// Codes beyond the tile configurations: one wave per small problem (M, N <=
+// 64) in binary32, or split precision with three or six products.
+constexpr int kBatchedSmall3 = 100, kBatchedSmall6 = 101, kBatchedSmall1 = 102;
 int batched_config(int path, int n_products, int64_t M, int64_t N, int64_t K, int64_t batch);
 gemm_status batched_run(int path, int cfg, const GemmArgs &g, int64_t sa, int64_t sb, int64_t sc,
                         int batch, hipStream_t s);

@@ -81,6 +81,42 @@ def test_shared_b_and_one_problem_equals_the_single_gemm():
         assert np.array_equal(d1.cpu().numpy(), d2.cpu().numpy()), n
 
 
+@pytest.mark.parametrize("M,N,K", [(32, 32, 32), (17, 29, 40), (64, 64, 64), (33, 64, 7),
+                                   (1, 1, 1), (64, 40, 100), (48, 16, 1000)])
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_small_problems_equal_the_tile_kernels_bitwise(M, N, K, n):
+    """Problems with M, N <= 64 run one wave per problem with fragments
+    loaded straight from memory; every element must be the same sum as in the
+    LDS-staged tile of the same arithmetic (n = 1: binary32 on the FP32
+    matrix cores; 3, 6: split products), run alone on the problem (gaps
+    between the problems never written)."""
+    import torch
+    import paper_1902_10345_amd as mm
+    path = mm.PATH_F32 if n == 1 else mm.PATH_3XBF16
+    batch = 9
+    g = np.random.default_rng(M * 1000 + N * 10 + K + n)
+    sa, sb, sc = M * K + 3, K * N + 5, M * N + 7
+    hA = g.uniform(-1, 1, size=batch * sa).astype(np.float32)
+    hB = g.uniform(-1, 1, size=batch * sb).astype(np.float32)
+    hC = g.uniform(-1, 1, size=batch * sc).astype(np.float32)
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (hA, hB, hC))
+    mm.gemm_strided_batched(path, M, N, K, 1.5, dA, K, sa, dB, N, sb, 0.5, dC, N, sc, batch,
+                            max(n, 3))
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    name = {1: "f32mfma_128x128x16_4w64x64", 3: "bx3_64x64x32_4w32x32_p3",
+            6: "bx3_128x128x32_4w64x64_p6"}[n]
+    cfg = [c for c in range(mm.gemm_num_configs(path)) if mm.gemm_config_name(path, c) == name][0]
+    for b in range(batch):
+        A = dA[b * sa:b * sa + M * K]
+        B = dB[b * sb:b * sb + K * N]
+        solo = torch.from_numpy(hC[b * sc:b * sc + M * N].copy()).cuda()
+        mm.gemm_run_config(path, cfg, M, N, K, 1.5, A, K, B, N, 0.5, solo, N, max(n, 3))
+        torch.cuda.synchronize()
+        assert np.array_equal(out[b * sc:b * sc + M * N], solo.cpu().numpy()), b
+        assert np.array_equal(out[b * sc + M * N:(b + 1) * sc], hC[b * sc + M * N:(b + 1) * sc])
+
+
 @pytest.mark.parametrize("path", ["f32", "3xbf16"])
 def test_more_problems_than_one_launch_exact(path):
     import torch
