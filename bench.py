@@ -330,6 +330,12 @@ def run_profile(torch, mm):
         mm.gemm_f64_strided_batched(ms_, ms_, ms_, 1.0, Ab, ms_, sz, Bb, ms_, sz, 0.0, Cb, ms_, sz,
                                     nb_)
     del Ab, Bb, Cb
+    Ab, Bb, Cb = (torch.rand(nb_ * sz, device="cuda") for _ in range(3))
+    for path in (mm.PATH_3XBF16, mm.PATH_F32):
+        for i in range(5):
+            mm.gemm_strided_batched(path, ms_, ms_, ms_, 1.0, Ab, ms_, sz, Bb, ms_, sz, 0.0, Cb, ms_,
+                                    sz, nb_, 3)
+    del Ab, Bb, Cb
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(5):
@@ -338,7 +344,8 @@ def run_profile(torch, mm):
     _log("profile run done: 5 x gemm_bx3, gemm_f32 (matrix cores and the vector-ALU tile), "
          "fp8_quantize, gemm_fp8, gemm_f64 (4096^3), "
          "5 x grouped 512, "
-         "5 x batched 32^3 x 29297 (binary64), 5 x copy of 1 GiB")
+         "5 x batched 32^3 x 29297 (binary64, then split precision and binary32), "
+         "5 x copy of 1 GiB")
 
 
 def _threads():

@@ -117,6 +117,39 @@ def test_small_problems_equal_the_tile_kernels_bitwise(M, N, K, n):
         assert np.array_equal(out[b * sc + M * N:(b + 1) * sc], hC[b * sc + M * N:(b + 1) * sc])
 
 
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_small_problems_with_padded_leading_dimensions(n):
+    """The one-wave-per-problem kernel with lda > K, ldb > N, ldc > N (A rows
+    not 16-byte aligned), against the oracle; padding never written."""
+    import torch
+    import paper_1902_10345_amd as mm
+    path = mm.PATH_F32 if n == 1 else mm.PATH_3XBF16
+    M, N, K, batch = 30, 21, 45, 7
+    lda, ldb, ldc = K + 3, N + 5, N + 2
+    sa, sb, sc = M * lda + 1, K * ldb, M * ldc + 4
+    g = np.random.default_rng(91 + n)
+    hA = g.uniform(-1, 1, size=batch * sa).astype(np.float32)
+    hB = g.uniform(-1, 1, size=batch * sb).astype(np.float32)
+    hC = g.uniform(-1, 1, size=batch * sc).astype(np.float32)
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (hA, hB, hC))
+    mm.gemm_strided_batched(path, M, N, K, -0.75, dA, lda, sa, dB, ldb, sb, 1.25, dC, ldc, sc,
+                            batch, max(n, 3))
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    for b in range(batch):
+        A = np.ascontiguousarray(hA[b * sa:b * sa + M * lda].reshape(M, lda)[:, :K])
+        B = np.ascontiguousarray(hB[b * sb:b * sb + K * ldb].reshape(K, ldb)[:, :N])
+        Cb = out[b * sc:b * sc + M * ldc].reshape(M, ldc)
+        C0 = hC[b * sc:b * sc + M * ldc].reshape(M, ldc)
+        got, c0 = np.ascontiguousarray(Cb[:, :N]), np.ascontiguousarray(C0[:, :N])
+        if n == 1:
+            _check_f32(A, B, c0, got, -0.75, 1.25)
+        else:
+            check_split_result(oracle, A, B, c0, got, -0.75, 1.25, n)
+        assert np.array_equal(Cb[:, N:], C0[:, N:])
+        assert np.array_equal(out[b * sc + M * ldc:(b + 1) * sc], hC[b * sc + M * ldc:(b + 1) * sc])
+
+
 @pytest.mark.parametrize("path", ["f32", "3xbf16"])
 def test_more_problems_than_one_launch_exact(path):
     import torch
