@@ -225,9 +225,10 @@ gemm_status gemm_f64_strided_batched(int64_t M, int64_t N, int64_t K, double alp
  * (binary32 products on the FP32 matrix cores) or GEMM_PATH_3XBF16
  * (n_products 3 or 6, as gemm_f32_3xbf16).  Output matrices must not
  * overlap: stride_c >= (M-1)*ldc + N when batch > 1.  Layout and quick
- * returns as gemm_f32; up to 65535 problems per launch.  Problems with M, N
- * <= 64 run one wave per problem (no LDS staging), with results bitwise those
- * of the library's matrix-core tiles of the same arithmetic.  Arguments: 1 path,
+ * returns as gemm_f32; up to 65535 problems per launch.  Small problems (M,
+ * N <= 64; with three products also M*N <= 48*48) run one wave per problem
+ * (no LDS staging), with results bitwise those of the library's matrix-core
+ * tiles of the same arithmetic.  Arguments: 1 path,
  * 2 M, 3 N, 4 K, 5 alpha, 6 A, 7 lda, 8 stride_a, 9 B, 10 ldb, 11 stride_b,
  * 12 beta, 13 C, 14 ldc, 15 stride_c, 16 batch, 17 n_products, 18 stream. */
 gemm_status gemm_strided_batched(int path, int64_t M, int64_t N, int64_t K, float alpha,
