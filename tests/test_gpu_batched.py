@@ -150,6 +150,29 @@ def test_small_problems_with_padded_leading_dimensions(n):
         assert np.array_equal(out[b * sc + M * ldc:(b + 1) * sc], hC[b * sc + M * ldc:(b + 1) * sc])
 
 
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_small_problems_beta_zero_never_read_c(n):
+    """beta == 0: C is write-only, so NaN in C must not reach the result."""
+    import torch
+    import paper_1902_10345_amd as mm
+    path = mm.PATH_F32 if n == 1 else mm.PATH_3XBF16
+    M, N, K, batch = 24, 40, 33, 5
+    A = si.uniform((batch * M, K), 81 + n).reshape(batch, M, K)
+    B = si.uniform((batch * K, N), 82 + n).reshape(batch, K, N)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.full((batch, M, N), float("nan"), device="cuda")
+    mm.gemm_strided_batched(path, M, N, K, 1.0, dA, K, M * K, dB, N, K * N, 0.0, dC, N, M * N,
+                            batch, max(n, 3))
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    assert np.isfinite(out).all()
+    for b in range(batch):
+        if n == 1:
+            _check_f32(A[b], B[b], None, out[b], 1.0, 0.0)
+        else:
+            check_split_result(oracle, A[b], B[b], None, out[b], 1.0, 0.0, n)
+
+
 @pytest.mark.parametrize("path", ["f32", "3xbf16"])
 def test_more_problems_than_one_launch_exact(path):
     import torch
