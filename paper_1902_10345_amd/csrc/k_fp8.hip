@@ -471,6 +471,12 @@ struct Fp8Cfg {
 
 __device__ __forceinline__ int swz8(int r) { return (r ^ (r >> 3)) & 7; }
 
+// Cache policy of the C stores: non-temporal (the slc bit of the buffer
+// instruction, NT on gfx950), a hint only.  C is written once at the end of a
+// tile; streaming it keeps the A and B code panels that the next round of
+// tiles reads in L2 (8192^2 x 4096: 329 -> 312 us; 4096^3 1 % faster).
+constexpr int kStoreNT = 2;
+
 // Epilogue of both FP8 kernels: C <- (sa[i] * (sb[j] * alpha)) * acc + beta * C
 // over the wave's FM x FN blocks of 32 x 32.  Through buffer resources over
 // the tile's valid part of C and of the scale vectors (rows and columns past
@@ -529,7 +535,8 @@ __device__ __forceinline__ void epilogue(const f32x16 (&acc)[FM][FN], int Mr, in
           float v = (si[e] * sj[j]) * acc[i][j][e];
           if (BETA) v = fmaf(beta, cold[j][e], v);
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rC, vb[j],
-                                                (r0 + 8 * (e >> 2) + (e & 3)) * ldc4, 0);
+                                                (r0 + 8 * (e >> 2) + (e & 3)) * ldc4,
+                                                kStoreNT);
         }
     }
     return;
