@@ -325,6 +325,14 @@ def test_strides_beyond_32_bit_tile_offsets_are_refused_before_launch():
                        0.0, F, 300, mm.PATH_3XBF16, 3, None, 0, None) == mm.STATUS_UNSUPPORTED
     assert lib.gemm_strided_batched(mm.PATH_3XBF16, 300, 300, 300, 1.0, F, big, 0, F, 300, 0, 0.0,
                                     F, 300, 90000, 2, 3, None) == mm.STATUS_UNSUPPORTED
+    # small problems (one wave per problem) refuse the same way on every path
+    # when neither their kernel nor the tile they fall back to can address the
+    # operands (ldb 2^25: a 16-deep slab of B spans 2^31 bytes)
+    for path, n in ((mm.PATH_3XBF16, 3), (mm.PATH_3XBF16, 6), (mm.PATH_F32, 3)):
+        assert lib.gemm_strided_batched(path, 32, 32, 32, 1.0, F, big, 0, F, 32, 0, 0.0, F, 32,
+                                        1024, 2, n, None) == mm.STATUS_UNSUPPORTED, (path, n)
+        assert lib.gemm_strided_batched(path, 32, 32, 32, 1.0, F, 32, 0, F, 2 * big, 0, 0.0, F,
+                                        32, 1024, 2, n, None) == mm.STATUS_UNSUPPORTED, (path, n)
 
 
 def test_default_config_of_empty_shapes():
