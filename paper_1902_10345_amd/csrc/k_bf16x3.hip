@@ -138,12 +138,13 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, const float *__re
 // registers, NP = 2 or 3 planes; NP = 1 is binary32 on the FP32 matrix
 // cores): every element is used by one wave only, so staging through LDS
 // would add traffic and barriers, and the 64 x 64 tile of four waves would
-// leave three of them on padding for a 32 x 32 problem.  A lane holds 8
-// consecutive k of its A row (two 128-bit loads) and of its B column (eight
-// loads, consecutive lanes on consecutive columns) per 16-deep k-step.  The
-// k-steps lie on the grid that ends at K (only the first can be partial) and
-// the products come in the tile kernels' order, so every element is the same
-// sum as in the LDS-staged tiles of the same product count.
+// leave three of them on padding for a 32 x 32 problem.  A lane holds 8 k of
+// its A row (two 128-bit loads) and of its B column (eight loads, consecutive
+// lanes on consecutive columns) per 16-deep k-step: 8 consecutive k on the
+// split path, two runs of 4 in binary32 (the FP32 tile's fragment order).
+// The k-steps lie on the grid that ends at K (only the first can be partial)
+// and the products come in the tile kernels' order, so every element is the
+// same sum as in the LDS-staged tile of the same arithmetic.
 // C stores with the non-temporal cache policy (the slc bit, NT on gfx950; a
 // hint only): 32^3 x 29 297 at beta = 0 63.2 -> 55.4 us, 48^3 x 12 000 63.6
 // -> 53.9 us.  The same hint on the operand loads was slower.
